@@ -1,0 +1,263 @@
+/*
+ * gpkmm.h - C ABI of an MI355X (gfx950) library for exact Gaussian-process
+ * training and prediction with never-materialised kernel-matrix products.
+ *
+ * The method is BBMM as used by Sun, Cheng & Miller, "Molecular Energy
+ * Learning Using Alternative Blackbox Matrix-Matrix Multiplication Algorithm
+ * for Exact Gaussian Process": the log marginal likelihood (Eq. 2), its
+ * gradient and the predictive equations (Eq. 1) are obtained from products
+ * K_hat V with K_hat = K(X, X) + sigma^2 I (Sec. 2.2), inside preconditioned
+ * modified batched CG (mBCG, Sec. 3.1-3.2) with a pivoted-Cholesky
+ * preconditioner (Sec. 3.2).  K_hat is recomputed tile by tile and never
+ * stored, so memory is O(N) (Sec. 3.2; the paper batches tiles of 4096 x 4096,
+ * Sec. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - X (n x d) and query rows Z (m x d) are FP64, row-major (point i occupies
+ *   X[i*d .. i*d+d-1]), in device memory.
+ * - A block of t vectors of length n ("columns") is FP64 and column-major:
+ *   column c starts at V + c*ldv, ldv >= n.
+ * - Every pointer documented "device" is a HIP device allocation owned by the
+ *   caller; "host" pointers are ordinary host memory.  The library never
+ *   frees, retains or reallocates caller memory after a call returns.
+ * - Scratch memory is the caller's: ws / ws_bytes, at least
+ *   gp_workspace_bytes(op, ...) bytes of device memory, 256-byte aligned.
+ * - stream is a hipStream_t (NULL: the null stream).  Calls whose outputs are
+ *   all in device memory are asynchronous on that stream; calls with host
+ *   outputs synchronise the stream before they return.
+ * - Return value: 0 on success, GP_WNOCONV (> 0) for a valid result that did
+ *   not meet its tolerance, a negative GP_E* code on error (outputs are then
+ *   unspecified).  Arguments are validated on the host before any GPU work;
+ *   gp_last_error() returns a message for the last non-zero status of the
+ *   calling thread.
+ * - Hyperparameter gradients are taken with respect to
+ *   (log l_1 .. log l_d, log s_f, log sigma^2), in that order (d + 2 values).
+ */
+#ifndef GPKMM_H
+#define GPKMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define GP_OK 0
+#define GP_WNOCONV 1       /* iteration limit hit; outputs valid */
+#define GP_EINVAL (-1)     /* bad argument (checked before any GPU work) */
+#define GP_EWORKSPACE (-2) /* ws NULL, misaligned or smaller than required */
+#define GP_EHIP (-3)       /* HIP runtime error (message from the runtime) */
+#define GP_ENOTPD (-4)     /* a curvature d^T K_hat d <= 0 or a factor not positive definite */
+#define GP_ENONFINITE (-5) /* NaN or Inf met in a reduction */
+
+/* ---- kernel families ---- */
+#define GP_MATERN52 0 /* k(r) = s_f (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r)  (Sec. 4) */
+#define GP_RBF 1      /* k(r) = s_f exp(-r^2/2) */
+
+/* ---- arithmetic of the kernel-matrix products ---- */
+#define GP_PREC_FP32 0   /* FP32 matrix-core operands and accumulation */
+#define GP_PREC_BF16X3 1 /* BF16 hi/lo split operands, three products, FP32 accumulation */
+
+#define GP_MAX_D 128 /* largest feature count d */
+
+/* ---- workspace query operation codes ---- */
+#define GP_OP_KMM 1
+#define GP_OP_KMM_GRAD 2
+#define GP_OP_PIVCHOL 3
+#define GP_OP_MBCG 4
+#define GP_OP_MLL 5
+#define GP_OP_PREDICT 6
+#define GP_OP_LANCZOS 7
+
+/*
+ * ARD stationary kernel with r^2 = sum_j ((x_j - z_j) / l_j)^2 (Sec. 2.2;
+ * Matern-5/2 per Sec. 4).  lengthscale: host, d entries, each finite and > 0.
+ * outputscale s_f > 0.  noise: the total sigma^2 >= 0 on the diagonal of
+ * K_hat (the paper adds a regulariser sigma^2_add to the optimised noise,
+ * Sec. 4; pass the sum).
+ */
+typedef struct gp_kernel {
+  int32_t kind;
+  int32_t d;
+  const double* lengthscale;
+  double outputscale;
+  double noise;
+} gp_kernel;
+
+/*
+ * Preconditioner P = L L^T + sigma^2 I from a rank-k pivoted Cholesky factor
+ * of K (Sec. 3.2).  rank = 0 means P = I (L and Cchol ignored).
+ * L: device, n x rank, column-major with leading dimension n.
+ * Cchol: device, rank x rank, column-major lower Cholesky factor of
+ * C = sigma^2 I + L^T L (upper triangle ignored).
+ */
+typedef struct gp_precond {
+  int32_t rank;
+  const double* L;
+  const double* Cchol;
+} gp_precond;
+
+/* Per-column record of an mBCG run (all host arrays, caller-allocated). */
+typedef struct gp_mbcg_out {
+  double* alpha;   /* nullable; max_iter x s, entry [j*s + c] = alpha of column c at iteration j */
+  double* beta;    /* nullable; same layout (0 after a column froze) */
+  int32_t* iters;  /* nullable; s entries: iterations J_c run by column c */
+  double* relres;  /* nullable; s entries: final ||r_c|| / ||b_c|| of the recurrence */
+  double* gamma0;  /* nullable; s entries: b_c^T P^{-1} b_c */
+  int32_t total_iters; /* out: iterations of the whole block */
+} gp_mbcg_out;
+
+/* Options of one marginal-likelihood evaluation. */
+typedef struct gp_mll_opts {
+  int32_t probes;    /* t >= 1 probe vectors (block is [y | b_1..b_t]) */
+  int32_t rank;      /* k >= 0 pivoted-Cholesky rank */
+  int32_t max_iter;  /* >= 1 */
+  int32_t precision; /* GP_PREC_* */
+  double tol;        /* relative residual at which a column freezes (0: run max_iter) */
+  uint64_t seed;     /* probe seed */
+} gp_mll_opts;
+
+/* Diagnostics of gp_mll_and_grad (host struct, nullable). */
+typedef struct gp_mll_info {
+  int32_t iters;      /* mBCG iterations run */
+  int32_t rank;       /* preconditioner rank reached */
+  double logdet;      /* SLQ estimate of log|K_hat| */
+  double logdet_p;    /* log|P| */
+  double quad;        /* y^T K_hat^{-1} y */
+  double max_relres;  /* largest final relative residual over the block */
+  double ms_precond, ms_mbcg, ms_grad; /* phase wall times */
+} gp_mll_info;
+
+/*
+ * gp_kmm - the kernel-matrix product (Sec. 3.1: CG needs only products with
+ * K_hat, each O(N^2), which are amenable to GPU acceleration).
+ *   Z == NULL : out = K_hat V = (K(X, X) + sigma^2 I) V, m ignored, out is n x t.
+ *   Z != NULL : out = K(Z, X) V (no noise), the cross-covariance product of the
+ *               predictive equations (Eq. 1); out is m x t.
+ * X: device n x d; Z: device m x d or NULL; V: device n x t (ldv >= n);
+ * out: device (n or m) x t (ldo >= rows), must not overlap V.
+ * n >= 1, 1 <= t <= 4096.  Asynchronous on stream.
+ */
+int gp_kmm(const gp_kernel* kern, int32_t precision,
+           const double* X, int64_t n, const double* Z, int64_t m,
+           const double* V, int64_t ldv, int32_t t,
+           double* out, int64_t ldo,
+           void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_kmm_grad - derivative bilinear forms for the gradient of Eq. 2:
+ *   grad[j] = sum_c colw[c] * U_c^T (dK_hat / dlog theta_j) W_c
+ * with dK_ab/dlog l_j = psi(r_ab) ((x_aj - x_bj)/l_j)^2, dK_hat/dlog s_f = K
+ * and dK_hat/dlog sigma^2 = sigma^2 I.  Tiles are recomputed, never stored.
+ * U, W: device n x t (ldu, ldw >= n); colw: host, t weights;
+ * grad: host, d + 2 values.  Synchronous.
+ */
+int gp_kmm_grad(const gp_kernel* kern, int32_t precision,
+                const double* X, int64_t n,
+                const double* U, int64_t ldu, const double* W, int64_t ldw, int32_t t,
+                const double* colw, double* grad,
+                void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_pivchol_precond - greedy rank-k pivoted Cholesky factor of K (without
+ * noise), the BBMM preconditioner (Sec. 3.2).  Pivot m is the unpivoted row
+ * with the largest residual diagonal (lowest index on ties); the factor stops
+ * early when that residual is <= 1e-12 s_f.  Also forms C = sigma^2 I + L^T L,
+ * its Cholesky factor, and log|P| = (n - rank) log sigma^2 + log|C|.
+ * Requires sigma^2 > 0 and 1 <= k <= min(n, 1024).
+ * L: device n x k (column-major, ld n; columns >= rank are zero);
+ * Cchol: device k x k; piv: host k entries (nullable); rank, logdetP: host.
+ * Synchronous.
+ */
+int gp_pivchol_precond(const gp_kernel* kern, const double* X, int64_t n, int32_t k,
+                       double* L, double* Cchol, int64_t* piv, int32_t* rank, double* logdetP,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_mbcg - modified batched preconditioned CG (Sec. 3.2): s independent CG
+ * recurrences on K_hat U = B sharing each product K_hat D.  Column c freezes
+ * once ||r_c|| <= tol ||b_c||.  FP64 recurrences; products per `precision`.
+ * pc: preconditioner (NULL: P = I); B: device n x s; U: device n x s output
+ * (K_hat^{-1} B); Z0: device n x s output P^{-1} B (nullable).  s <= 256.
+ * Synchronises once per iteration.  Returns GP_WNOCONV if some column had
+ * not converged after max_iter iterations (tol > 0).
+ */
+int gp_mbcg(const gp_kernel* kern, int32_t precision,
+            const double* X, int64_t n, const gp_precond* pc,
+            const double* B, int32_t s, int32_t max_iter, double tol,
+            double* U, double* Z0, gp_mbcg_out* out,
+            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_probe_block - the right-hand-side block [y | b_1..b_t] (Sec. 3.1 sets
+ * y_0 = y and random y_i), with Rademacher probes b_i = L e1_i + sigma e2_i
+ * (E[b b^T] = P) or b_i = e2_i when k = 0.  Signs: top bit of one SplitMix64
+ * step from key ^ ((stream << 40) | row), key = one step from seed; probe i uses
+ * stream i for e2 and i + 65536 for e1.
+ * y: device n; L: device n x k (ld n) or NULL when k = 0; B: device n x (t+1).
+ */
+int gp_probe_block(const double* y, int64_t n, int32_t t, const double* L, int32_t k,
+                   double noise, uint64_t seed, double* B, void* stream);
+
+/*
+ * gp_mll_and_grad - one BBMM evaluation of the log marginal likelihood (Eq. 2)
+ * and of its gradient: pivoted-Cholesky preconditioner, probe block,
+ * mBCG, stochastic Lanczos quadrature for log|K_hat| and stochastic trace
+ * estimates for the gradient (Sec. 3.2).
+ * X: device n x d; y: device n; mll: host; grad: host d + 2 (nullable: no
+ * gradient); info: host (nullable).  Synchronous.
+ */
+int gp_mll_and_grad(const gp_kernel* kern, const gp_mll_opts* opts,
+                    const double* X, const double* y, int64_t n,
+                    double* mll, double* grad, gp_mll_info* info,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_lanczos_cache - rank-kc Lanczos decomposition K_hat Q = Q T (full FP64
+ * re-orthogonalisation, start y / ||y||) and the variance cache
+ * R = Q L_T^{-T} with T = L_T L_T^T, so that R R^T = Q T^{-1} Q^T ~ K_hat^{-1}
+ * for the variance of Eq. 1.  R: device n x kc (ld n); kc_out: host, the rank
+ * reached (< kc if the Krylov space closed).  Synchronous.
+ */
+int gp_lanczos_cache(const gp_kernel* kern, int32_t precision,
+                     const double* X, const double* y, int64_t n, int32_t kc,
+                     double* R, int32_t* kc_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_predict - predictive mean K(Z, X) alpha and latent variance
+ * s_f - ||K(z, X) R||^2 at m query rows (Eq. 1, with the prior term that the
+ * printed variance leaves out), from alpha = K_hat^{-1} y and a variance cache
+ * R.  X: device n x d; alpha: device n; R: device n x kc (ld n) or NULL;
+ * Z: device m x d; mean: device m; var: device m (nullable; needs R).
+ * Each row's result depends only on that row (not on the other rows of the
+ * call).  Asynchronous.
+ */
+int gp_predict(const gp_kernel* kern, int32_t precision,
+               const double* X, int64_t n, const double* alpha,
+               const double* R, int32_t kc,
+               const double* Z, int64_t m, double* mean, double* var,
+               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_workspace_bytes - device scratch needed by one call of `op`
+ * (GP_OP_*), for n training rows, m query rows, d features, t columns
+ * (probes + 1 for GP_OP_MLL: pass opts.probes), k preconditioner rank (or kc
+ * for GP_OP_LANCZOS / GP_OP_PREDICT).  Returns 0 for invalid arguments.
+ */
+size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d, int32_t t,
+                          int32_t k, int32_t precision);
+
+/* Message of the last non-zero status returned to the calling thread. */
+const char* gp_last_error(void);
+
+/* Library version string. */
+const char* gp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPKMM_H */

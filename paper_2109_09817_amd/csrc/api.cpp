@@ -1,0 +1,87 @@
+// C ABI: argument validation, error reporting, workspace sizing and gp_kmm.
+#include <algorithm>
+
+#include "api_common.h"
+#include "internal.h"
+
+namespace gpk {
+
+std::string& last_error() {
+  static thread_local std::string msg;
+  return msg;
+}
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  last_error() = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what, int line) {
+  return fail(GP_EHIP, "HIP error %d (%s) at %s [line %d]", (int)e, hipGetErrorString(e), what, line);
+}
+
+int check_kernel(const gp_kernel* k) {
+  if (!k) return fail(GP_EINVAL, "kernel descriptor is NULL");
+  if (k->kind != GP_MATERN52 && k->kind != GP_RBF) return fail(GP_EINVAL, "unknown kernel kind %d", k->kind);
+  if (k->d < 1 || k->d > GP_MAX_D) return fail(GP_EINVAL, "feature count d=%d outside [1, %d]", k->d, GP_MAX_D);
+  if (!k->lengthscale) return fail(GP_EINVAL, "lengthscale pointer is NULL");
+  for (int j = 0; j < k->d; ++j)
+    if (!std::isfinite(k->lengthscale[j]) || !(k->lengthscale[j] > 0.0))
+      return fail(GP_EINVAL, "lengthscale[%d]=%g must be finite and > 0", j, k->lengthscale[j]);
+  if (!std::isfinite(k->outputscale) || !(k->outputscale > 0.0))
+    return fail(GP_EINVAL, "outputscale=%g must be finite and > 0", k->outputscale);
+  if (!std::isfinite(k->noise) || k->noise < 0.0) return fail(GP_EINVAL, "noise=%g must be finite and >= 0", k->noise);
+  return GP_OK;
+}
+
+int check_precision(int32_t p) {
+  if (p != GP_PREC_FP32 && p != GP_PREC_BF16X3) return fail(GP_EINVAL, "unknown precision %d", p);
+  return GP_OK;
+}
+
+int check_ws(const void* ws, size_t have, size_t need, const char* op) {
+  if (need == 0) return GP_OK;
+  if (!ws) return fail(GP_EWORKSPACE, "%s: workspace is NULL (%zu bytes needed)", op, need);
+  if (((uintptr_t)ws & 255) != 0) return fail(GP_EWORKSPACE, "%s: workspace not 256-byte aligned", op);
+  if (have < need) return fail(GP_EWORKSPACE, "%s: workspace has %zu bytes, %zu needed", op, have, need);
+  return GP_OK;
+}
+
+}  // namespace gpk
+
+using namespace gpk;
+
+extern "C" const char* gp_last_error(void) { return last_error().c_str(); }
+
+extern "C" const char* gp_version(void) { return "gpkmm 0.1 (gfx950)"; }
+
+extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z,
+                      int64_t m, const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws,
+                      size_t ws_bytes, void* stream) {
+  GPK_TRY(check_kernel(kern));
+  GPK_TRY(check_precision(precision));
+  if (!X) return fail(GP_EINVAL, "gp_kmm: X is NULL");
+  if (n < 1) return fail(GP_EINVAL, "gp_kmm: n=%lld must be >= 1", (long long)n);
+  if (Z && m < 1) return fail(GP_EINVAL, "gp_kmm: m=%lld must be >= 1 when Z is given", (long long)m);
+  if (!V || !out) return fail(GP_EINVAL, "gp_kmm: V or out is NULL");
+  if (t < 1 || t > 4096) return fail(GP_EINVAL, "gp_kmm: t=%d outside [1, 4096]", t);
+  if (ldv < n) return fail(GP_EINVAL, "gp_kmm: ldv=%lld < n=%lld", (long long)ldv, (long long)n);
+  const int64_t rows = Z ? m : n;
+  if (ldo < rows) return fail(GP_EINVAL, "gp_kmm: ldo=%lld < %lld output rows", (long long)ldo, (long long)rows);
+  if ((const void*)out == (const void*)V) return fail(GP_EINVAL, "gp_kmm: out must not alias V");
+  const bool square = Z == nullptr;
+  const size_t need = kmm_plan_bytes(precision, kern->d, n, rows, square, t);
+  GPK_TRY(check_ws(ws, ws_bytes, need, "gp_kmm"));
+  KmmPlan p;
+  if (!kmm_plan_init(p, kern, precision, n, rows, square, t, ws, ws_bytes))
+    return fail(GP_EWORKSPACE, "gp_kmm: workspace layout failed");
+  hipStream_t st = (hipStream_t)stream;
+  GPK_HIP(kmm_prepare(p, kern, X, Z, st));
+  GPK_HIP(kmm_apply(p, V, ldv, t, out, ldo, st, /*row_independent=*/!square));
+  return GP_OK;
+}

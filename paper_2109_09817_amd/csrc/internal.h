@@ -1,0 +1,69 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of libgpkmm.  Not part of the public ABI (see include/gpkmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gpkmm.h"
+
+namespace gpk {
+
+// Feature scaling passed by value to the preparation kernels: x~_j = x_j * s[j].
+struct Scale {
+  double s[GP_MAX_D];
+};
+
+// Geometry of one prepared kernel-matrix product (square K_hat V or cross K(Z, X) V).
+//
+// Operand streams (all in caller workspace):
+//   xr   "row side" fragments of the n training points: they play the column
+//        (summation) index b of the product and feed the distance MFMA as its
+//        A operand; the stream every workgroup sweeps.
+//   xc   "column side" fragments of the output rows a (training points for
+//        the square product, query rows for the cross product); they stay in
+//        registers for a workgroup's whole sweep.
+//   vf   the right-hand sides V split into MFMA B-operand fragments.
+//   part FP64 partial sums per split of the b range.
+struct KmmPlan {
+  int precision = 0;  // GP_PREC_*
+  int kind = 0;       // GP_MATERN52 / GP_RBF
+  int d = 0;
+  bool square = true;
+  int64_t n = 0, m = 0;         // training rows, output rows
+  int64_t npad = 0, mpad = 0;   // n rounded to 32, m rounded to 256
+  int64_t nchunks = 0;          // npad / 32
+  int ks = 0;                   // K steps: 32-wide (BF16X3) or 16-wide float4 groups (FP32)
+  int tmax = 0;                 // columns the plan was sized for
+  int ntb = 0;                  // 16-column blocks for tmax
+  double sf = 1.0, noise = 0.0;
+  // workspace carve-out
+  void* xr = nullptr;
+  void* xc = nullptr;
+  float* nrm_b = nullptr;   // FP32 form: norms of the b stream
+  float* nrm_a = nullptr;   // FP32 form: norms of the output rows
+  double* nrm64 = nullptr;  // FP64 norms scratch (n or m entries)
+  void* vf = nullptr;
+  double* part = nullptr;
+  int64_t part_splits = 0;  // splits the partial buffer can hold
+};
+
+// Number of 32-wide K steps (BF16X3) or 16-wide groups (FP32) for d features.
+int kmm_ksteps(int precision, int d);
+// Bytes of workspace for a plan (square: Z == X).
+size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, int tmax);
+// Carve a plan out of ws (no GPU work).  Returns false if ws is too small.
+bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, int64_t m,
+                   bool square, int tmax, void* ws, size_t ws_bytes);
+// Prepare the point operands (X, and Z for a cross product).
+hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const double* Z,
+                       hipStream_t st);
+// out = K_hat V (square) or K(Z, X) V (cross), V column-major (ldv), t <= tmax columns.
+// Splits of the b range are chosen from n only when `row_independent` is set,
+// so that each output row's arithmetic does not depend on m.
+hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out,
+                     int64_t ldo, hipStream_t st, bool row_independent = false);
+
+}  // namespace gpk

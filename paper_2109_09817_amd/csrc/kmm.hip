@@ -1,0 +1,728 @@
+// Fused, never-materialised kernel-matrix products for gfx950.
+//
+//   square:  W = K_hat V = s_f M(X, X) V + sigma^2 V,  M_ab = m(r_ab)
+//   cross:   W = K(Z, X) V = s_f M(Z, X) V
+//
+// with r_ab^2 = sum_j ((x_aj - x_bj)/l_j)^2 and m the Matern-5/2 or RBF
+// profile (the kernel of Sec. 4; K_hat of Sec. 2.2; the O(N^2) product that
+// CG needs, Sec. 3.1, never stored, Sec. 3.2).
+//
+// One workgroup = 4 wave64s, each owning 16*NA output rows a.  A wave keeps
+// the MFMA fragments of its rows in registers and sweeps the b stream in
+// chunks of 32 points.  Per (16-row block, 32-point chunk):
+//   1. S = XR_b . XC_a^T on the matrix cores gives r^2 directly: the operands
+//      carry -2 x~_b against x~_a plus the two squared norms folded into the
+//      K padding, so no VALU work builds the distance.
+//   2. m(r) is evaluated in registers on the S accumulator (v_sqrt, v_exp,
+//      two FMAs); the accumulator layout (lane = a, 4 consecutive b per lane
+//      group) is already the A-operand layout of the next product once the
+//      K index of that product is permuted to match, so nothing goes through
+//      LDS.
+//   3. acc += M . V_b on the matrix cores.
+// FP32 accumulators are flushed to FP64 every FLUSH chunks.  The diagonal
+// element of the square product is masked out of the tiles and added exactly
+// in FP64 by the epilogue as (s_f + sigma^2) V.
+//
+// Two arithmetic forms share this structure:
+//   BF16X3: operands split x = hi + lo in BF16 (round to nearest even), the
+//           three products hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16,
+//           FP32 accumulation; M is split the same way for the second product.
+//   FP32:   v_mfma_f32_16x16x4_f32 for both products; the squared norms
+//           initialise the distance accumulator.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace gpk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+
+// log2(e) * sqrt(5) scales x/l so that S = u^2 with u = sqrt5 r log2(e):
+// exp(-sqrt5 r) = exp2(-u) and 1 + sqrt5 r + 5r^2/3 = 1 + u ln2 + (u ln2)^2 / 3.
+constexpr double kMaternScale = 3.2259795535340955;  // sqrt(5) * log2(e)
+constexpr float kMaternC1 = 0.6931471805599453f;     // ln 2
+constexpr float kMaternC2 = 0.16015100463940034f;    // (ln 2)^2 / 3
+// RBF: S = r^2 log2(e) / 2 so that exp(-r^2/2) = exp2(-S).
+constexpr double kRbfScale = 0.8493218002880191;     // sqrt(log2(e) / 2)
+
+constexpr int kFlush = 32;  // 32-point chunks accumulated in FP32 before the FP64 flush
+
+// The profile m(r) from S = r^2 scaled as above.  ACCURATE replaces the raw
+// v_sqrt_f32 by v_rsq_f32 plus one Newton step on the residual S - u^2; the raw
+// instruction's relative error (~1e-5 at worst) then drops to a few ulp.  The
+// FP32 form uses it (its VALU work is hidden behind the slower FP32 matrix
+// cores); in the BF16X3 form the BF16 splits dominate the error.
+template <int KIND, bool ACCURATE>
+__device__ __forceinline__ float profile(float S) {
+  if constexpr (KIND == GP_MATERN52) {
+    float u;
+    if constexpr (ACCURATE) {
+      const float s = __builtin_fmaxf(__builtin_fabsf(S), 1e-30f);
+      const float y = __builtin_amdgcn_rsqf(s);
+      const float u0 = s * y;
+      u = __builtin_fmaf(__builtin_fmaf(-u0, u0, s), 0.5f * y, u0);
+    } else {
+      u = __builtin_amdgcn_sqrtf(__builtin_fabsf(S));
+    }
+    const float e = __builtin_amdgcn_exp2f(-u);
+    const float poly = __builtin_fmaf(__builtin_fmaf(u, kMaternC2, kMaternC1), u, 1.0f);
+    return poly * e;
+  } else {
+    return __builtin_amdgcn_exp2f(-__builtin_fabsf(S));
+  }
+}
+
+__device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(float)x; }
+
+// ---------------------------------------------------------------- preparation
+
+// Squared norm of each prepared point (FP64).  BF16X3: n = sum(h^2 + 2 h l), so
+// that the MFMA distance equals |dx'|^2 - |dl|^2 (x' = h + l): its error is
+// relative to the true distance.  FP32: n = sum(f^2) with f = fl32(x~).
+__global__ void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad, int d,
+                                 Scale sc, int mixed, double* __restrict__ nrm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npad) return;
+  double s = 0.0;
+  if (p < n) {
+    const double* x = X + p * d;
+    for (int j = 0; j < d; ++j) {
+      const double v = x[j] * sc.s[j];
+      if (mixed) {
+        const double h = bf16_round(v);
+        const double l = bf16_round(v - h);
+        s += h * h + 2.0 * h * l;
+      } else {
+        const double f = (float)v;
+        s += f * f;
+      }
+    }
+  }
+  nrm[p] = s;
+}
+
+// BF16X3 point fragments.  K layout of a prepared point (length 32*KS, zero padded):
+//   row side (b):    [-2h_0..-2h_{d-1}, -2h_0.., -2l_0.., nhi, nmid, nlo, 1, 1, 1, 0..]
+//   column side (a): [  h_0..  h_{d-1},   l_0..,   h_0.., 1, 1, 1, nhi, nmid, nlo, 0..]
+// so that sum_K row*col = -2(h.h + h.l + l.h) + n_b + n_a.  Fragment (blk, ks, lane)
+// holds K = 32 ks + 8 (lane/16) + j, j = 0..7, of point 16 blk + lane%16.
+__global__ void prep_frag_bf16x3_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
+                                        int64_t n, int64_t nblk, int d, int KS, Scale sc,
+                                        bf16x8* __restrict__ xr, bf16x8* __restrict__ xc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nblk * KS * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int ks = (int)(rest % KS);
+  const int64_t blk = rest / KS;
+  const int64_t p = blk * 16 + (lane & 15);
+  const int g = lane >> 4;
+  bf16x8 r, c;
+  float nhi = 0.f, nmid = 0.f, nlo = 0.f;
+  if (p < n) {
+    const double nn = nrm[p];
+    nhi = bf16_round(nn);
+    nmid = bf16_round(nn - (double)nhi);
+    nlo = bf16_round(nn - (double)nhi - (double)nmid);
+  }
+  for (int j = 0; j < 8; ++j) {
+    const int k = 32 * ks + 8 * g + j;
+    float rv = 0.f, cv = 0.f;
+    if (p < n) {
+      if (k < 3 * d) {
+        const int seg = k / d, f = k - seg * d;
+        const double v = X[p * d + f] * sc.s[f];
+        const float h = bf16_round(v);
+        const float l = bf16_round(v - (double)h);
+        rv = -2.f * (seg == 2 ? l : h);
+        cv = (seg == 1 ? l : h);
+      } else if (k < 3 * d + 3) {
+        const int q = k - 3 * d;
+        rv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
+        cv = 1.f;
+      } else if (k < 3 * d + 6) {
+        const int q = k - 3 * d - 3;
+        rv = 1.f;
+        cv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
+      }
+    }
+    r[j] = (__bf16)rv;
+    c[j] = (__bf16)cv;
+  }
+  if (xr) xr[idx] = r;
+  if (xc) xc[idx] = c;
+}
+
+// FP32 point fragments: float4 (blk, q, lane) = f(point 16 blk + lane%16, feature
+// 16 q + 4 s + lane/16) for s = 0..3, f = -2 x~ (row side) or x~ (column side).
+__global__ void prep_frag_fp32_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
+                                      int64_t n, int64_t nblk, int d, int KQ, Scale sc,
+                                      f32x4* __restrict__ xr, f32x4* __restrict__ xc,
+                                      float* __restrict__ nrm_r, float* __restrict__ nrm_c) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nblk * KQ * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int q = (int)(rest % KQ);
+  const int64_t blk = rest / KQ;
+  const int64_t p = blk * 16 + (lane & 15);
+  const int g = lane >> 4;
+  f32x4 r, c;
+  for (int s = 0; s < 4; ++s) {
+    const int f = 16 * q + 4 * s + g;
+    float v = 0.f;
+    if (p < n && f < d) v = (float)(X[p * d + f] * sc.s[f]);
+    r[s] = -2.f * v;
+    c[s] = v;
+  }
+  if (xr) xr[idx] = r;
+  if (xc) xc[idx] = c;
+  if (q == 0 && g == 0) {
+    const float nv = p < n ? (float)nrm[p] : 0.f;
+    if (nrm_r) nrm_r[p] = nv;
+    if (nrm_c) nrm_c[p] = nv;
+  }
+}
+
+// K index permutation of the M . V product: slot (g, j) of a lane holds point
+// b = 4g + j (j < 4) or 16 + 4g + j - 4 (j >= 4) of the 32-point chunk, which is
+// where the two distance tiles' accumulators leave them.
+__device__ __forceinline__ int vperm(int g, int j) { return j < 4 ? 4 * g + j : 12 + 4 * g + j; }
+
+// BF16X3 V fragments: (chunk, cb, hl, lane) -> 8 BF16 of V[b = 32 chunk + vperm(g, j)]
+// [c = 16 cb + lane%16], hl = 0 hi, 1 lo.
+__global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, int64_t n, int t,
+                                     int64_t nchunks, int ntb, bf16x8* __restrict__ vf) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nchunks * ntb * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int cb = (int)(rest % ntb);
+  const int64_t ch = rest / ntb;
+  const int c = 16 * cb + (lane & 15);
+  const int g = lane >> 4;
+  bf16x8 hi, lo;
+  for (int j = 0; j < 8; ++j) {
+    const int64_t b = ch * 32 + vperm(g, j);
+    const double v = (b < n && c < t) ? V[(int64_t)c * ldv + b] : 0.0;
+    const float h = bf16_round(v);
+    hi[j] = (__bf16)h;
+    lo[j] = (__bf16)(float)(v - (double)h);
+  }
+  vf[(rest * 2 + 0) * 64 + lane] = hi;
+  vf[(rest * 2 + 1) * 64 + lane] = lo;
+}
+
+// FP32 V fragments: (chunk, cb, tile, lane) -> float4 of V[b = 32 chunk + 16 tile + 4g + i]
+// [c = 16 cb + lane%16], i = 0..3.
+__global__ void prep_v_fp32_kernel(const double* __restrict__ V, int64_t ldv, int64_t n, int t,
+                                   int64_t nchunks, int ntb, f32x4* __restrict__ vf) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nchunks * ntb * 2 * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;  // (ch * ntb + cb) * 2 + tile
+  const int tile = (int)(rest & 1);
+  const int64_t cbch = rest >> 1;
+  const int cb = (int)(cbch % ntb);
+  const int64_t ch = cbch / ntb;
+  const int c = 16 * cb + (lane & 15);
+  const int g = lane >> 4;
+  f32x4 o;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t b = ch * 32 + 16 * tile + 4 * g + i;
+    o[i] = (b < n && c < t) ? (float)V[(int64_t)c * ldv + b] : 0.f;
+  }
+  vf[idx] = o;
+}
+
+// ------------------------------------------------------------------ main sweep
+
+struct SweepArgs {
+  const void* xr;
+  const void* xc;
+  const float* nrm_b;
+  const float* nrm_a;
+  const void* vf;
+  double* part;
+  int64_t mpad;
+  int64_t nchunks;
+  int64_t cps;   // chunks per split
+  int ntb;       // 16-column blocks in vf
+  int tpad;      // columns of the partial buffer
+  int square;    // mask the diagonal (square product)
+};
+
+template <int NT>
+struct NAOf {
+  static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+};
+
+template <int KS, int NT, int KIND>
+__global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
+  constexpr int NA = NAOf<NT>::value;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int64_t ablk0 = ((int64_t)blockIdx.x * 4 + wave) * NA;
+  if (ablk0 * 16 >= a.mpad) return;
+  const int cb0 = blockIdx.z * NT;
+  const bf16x8* __restrict__ xr = (const bf16x8*)a.xr;
+  const bf16x8* __restrict__ xc = (const bf16x8*)a.xc;
+  const bf16x8* __restrict__ vf = (const bf16x8*)a.vf;
+
+  bf16x8 A[NA][KS];
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) A[ab][ks] = xc[((ablk0 + ab) * KS + ks) * 64 + lane];
+
+  double acc64[NA][NT][4];
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc64[ab][cb][i] = 0.0;
+
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cps;
+  const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += kFlush) {
+    const int64_t c1 = c0 + kFlush < c_end ? c0 + kFlush : c_end;
+    f32x4 acc[NA][NT];
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) acc[ab][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t ch = c0; ch < c1; ++ch) {
+      bf16x8 B0[KS], B1[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        B0[ks] = xr[((2 * ch) * KS + ks) * 64 + lane];
+        B1[ks] = xr[((2 * ch + 1) * KS + ks) * 64 + lane];
+      }
+      bf16x8 VH[NT], VL[NT];
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) {
+        const int64_t base = ((ch * a.ntb + cb0 + cb) * 2) * 64 + lane;
+        VH[cb] = vf[base];
+        VL[cb] = vf[base + 64];
+      }
+#pragma unroll
+      for (int ab = 0; ab < NA; ++ab) {
+        f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
+          s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
+        }
+        f32x8 mv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          mv[i] = profile<KIND, false>(s0[i]);
+          mv[4 + i] = profile<KIND, false>(s1[i]);
+        }
+        if (a.square) {
+          const int64_t arow = (ablk0 + ab) * 16;
+          if (arow == ch * 32 || arow == ch * 32 + 16) {
+            const int off = arow == ch * 32 ? 0 : 4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((lane & 15) == 4 * g + i) mv[off + i] = 0.f;
+          }
+        }
+        const bf16x8 H = __builtin_convertvector(mv, bf16x8);
+        const f32x8 hf = __builtin_convertvector(H, f32x8);
+        const bf16x8 L = __builtin_convertvector(mv - hf, bf16x8);
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) {
+          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VH[cb], acc[ab][cb], 0, 0, 0);
+          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VL[cb], acc[ab][cb], 0, 0, 0);
+          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, VH[cb], acc[ab][cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc64[ab][cb][i] += (double)acc[ab][cb][i];
+  }
+  // partial[(split * tpad + col) * mpad + row]
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb) {
+      const int64_t col = (int64_t)(cb0 + cb) * 16 + (lane & 15);
+      const int64_t row = (ablk0 + ab) * 16 + 4 * g;
+      double* dst = a.part + ((int64_t)blockIdx.y * a.tpad + col) * a.mpad + row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[i] = acc64[ab][cb][i];
+    }
+}
+
+template <int KQ, int NT, int KIND>
+__global__ __launch_bounds__(256, 2) void sweep_fp32_kernel(SweepArgs a) {
+  constexpr int NA = NAOf<NT>::value;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int64_t ablk0 = ((int64_t)blockIdx.x * 4 + wave) * NA;
+  if (ablk0 * 16 >= a.mpad) return;
+  const int cb0 = blockIdx.z * NT;
+  const f32x4* __restrict__ xr = (const f32x4*)a.xr;
+  const f32x4* __restrict__ xc = (const f32x4*)a.xc;
+  const f32x4* __restrict__ vf = (const f32x4*)a.vf;
+
+  f32x4 A[NA][KQ];
+  float na[NA];
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) A[ab][q] = xc[((ablk0 + ab) * KQ + q) * 64 + lane];
+    na[ab] = a.nrm_a[(ablk0 + ab) * 16 + (lane & 15)];
+  }
+  double acc64[NA][NT][4];
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc64[ab][cb][i] = 0.0;
+
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cps;
+  const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += kFlush) {
+    const int64_t c1 = c0 + kFlush < c_end ? c0 + kFlush : c_end;
+    f32x4 acc[NA][NT];
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) acc[ab][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t ch = c0; ch < c1; ++ch) {
+      f32x4 B0[KQ], B1[KQ];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        B0[q] = xr[((2 * ch) * KQ + q) * 64 + lane];
+        B1[q] = xr[((2 * ch + 1) * KQ + q) * 64 + lane];
+      }
+      const f32x4 nb0 = *(const f32x4*)(a.nrm_b + ch * 32 + 4 * g);
+      const f32x4 nb1 = *(const f32x4*)(a.nrm_b + ch * 32 + 16 + 4 * g);
+      f32x4 V0[NT], V1[NT];
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) {
+        const int64_t base = ((ch * a.ntb + cb0 + cb) * 2) * 64 + lane;
+        V0[cb] = vf[base];
+        V1[cb] = vf[base + 64];
+      }
+#pragma unroll
+      for (int ab = 0; ab < NA; ++ab) {
+        f32x4 s0 = nb0 + na[ab];
+        f32x4 s1 = nb1 + na[ab];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(B0[q][s], A[ab][q][s], s0, 0, 0, 0);
+            s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(B1[q][s], A[ab][q][s], s1, 0, 0, 0);
+          }
+        f32x4 m0, m1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          m0[i] = profile<KIND, true>(s0[i]);
+          m1[i] = profile<KIND, true>(s1[i]);
+        }
+        if (a.square) {
+          const int64_t arow = (ablk0 + ab) * 16;
+          if (arow == ch * 32) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((lane & 15) == 4 * g + i) m0[i] = 0.f;
+          } else if (arow == ch * 32 + 16) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((lane & 15) == 4 * g + i) m1[i] = 0.f;
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(m0[i], V0[cb][i], acc[ab][cb], 0, 0, 0);
+            acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(m1[i], V1[cb][i], acc[ab][cb], 0, 0, 0);
+          }
+      }
+    }
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc64[ab][cb][i] += (double)acc[ab][cb][i];
+  }
+#pragma unroll
+  for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb) {
+      const int64_t col = (int64_t)(cb0 + cb) * 16 + (lane & 15);
+      const int64_t row = (ablk0 + ab) * 16 + 4 * g;
+      double* dst = a.part + ((int64_t)blockIdx.y * a.tpad + col) * a.mpad + row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[i] = acc64[ab][cb][i];
+    }
+}
+
+// out[c*ldo + r] = s_f * sum_split part + (square ? (s_f + sigma^2) V[c*ldv + r] : 0)
+__global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsplit, int tpad,
+                                    int64_t mpad, int64_t m, int t, double sf, double diag,
+                                    const double* __restrict__ V, int64_t ldv,
+                                    double* __restrict__ out, int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * t) return;
+  const int64_t c = idx / m, r = idx - c * m;
+  double s = 0.0;
+  for (int64_t sp = 0; sp < nsplit; ++sp) s += part[(sp * tpad + c) * mpad + r];
+  double o = sf * s;
+  if (V) o += diag * V[c * ldv + r];
+  out[c * ldo + r] = o;
+}
+
+// ------------------------------------------------------------------ host side
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int kmm_ksteps(int precision, int d) {
+  if (precision == GP_PREC_BF16X3) {
+    const int need = (3 * d + 6 + 31) / 32;
+    static const int kAvail[] = {2, 4, 5, 7, 10, 13};
+    for (int k : kAvail)
+      if (k >= need) return k;
+    return -1;
+  }
+  const int need = (d + 15) / 16;
+  static const int kAvail32[] = {1, 2, 3, 4, 6, 8};
+  for (int k : kAvail32)
+    if (k >= need) return k;
+  return -1;
+}
+
+// Column blocks handled per launch (grid.z groups the rest).
+static int nt_launch(int ntb) { return ntb >= 4 ? 4 : ntb; }
+static int na_of(int nt) { return nt == 1 ? 4 : (nt == 2 ? 2 : 1); }
+
+struct SplitChoice {
+  int nt, groups, tpad;
+  int64_t cps, nsplit;
+};
+
+static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_independent) {
+  SplitChoice s;
+  s.nt = nt_launch(ntb);
+  s.groups = (ntb + s.nt - 1) / s.nt;
+  s.tpad = s.groups * s.nt * 16;
+  const int64_t nchunks = npad / 32;
+  if (row_independent) {
+    // depends on n only: each output row sees the same chunk boundaries whatever m is
+    s.cps = std::max<int64_t>(8, (nchunks + 63) / 64);
+  } else {
+    const int64_t row_wgs = mpad / (64 * na_of(s.nt)) * s.groups;
+    const int64_t want = std::max<int64_t>(1, (2048 + row_wgs - 1) / row_wgs);
+    s.cps = std::max<int64_t>(2, (nchunks + want - 1) / want);
+  }
+  s.nsplit = (nchunks + s.cps - 1) / s.cps;
+  return s;
+}
+
+static size_t part_bytes_max(int64_t npad, int64_t mpad, int ntb, bool row_independent) {
+  size_t best = 0;
+  for (int nb = 1; nb <= ntb; ++nb) {
+    const SplitChoice s = choose_split(npad, mpad, nb, row_independent);
+    best = std::max(best, (size_t)s.nsplit * s.tpad * mpad * sizeof(double));
+  }
+  return best;
+}
+
+size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, int tmax) {
+  const int ks = kmm_ksteps(precision, d);
+  if (ks < 0) return 0;
+  const int64_t npad = round_up(n, 32);
+  const int64_t mrows = square ? n : m;
+  const int64_t mpad = round_up(mrows, 256);
+  const int64_t bpad = std::max(npad, mpad);  // the square case prepares mpad rows of X
+  const int ntb0 = (tmax + 15) / 16;
+  const int ntb = (ntb0 + nt_launch(ntb0) - 1) / nt_launch(ntb0) * nt_launch(ntb0);
+  size_t b = 0;
+  b += align256((size_t)bpad * ks * 64);           // xr
+  b += align256((size_t)mpad * ks * 64);           // xc
+  b += align256((size_t)bpad * 4);                 // nrm_b
+  b += align256((size_t)mpad * 4);                 // nrm_a
+  b += align256((size_t)bpad * 8);                 // nrm64
+  b += align256((size_t)npad * ntb * 64 + 64);     // vf
+  b += align256(part_bytes_max(npad, mpad, ntb0, !square));  // partials
+  return b;
+}
+
+bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, int64_t m,
+                   bool square, int tmax, void* ws, size_t ws_bytes) {
+  const size_t need = kmm_plan_bytes(precision, kern->d, n, m, square, tmax);
+  if (need == 0 || ws == nullptr || ws_bytes < need) return false;
+  p.precision = precision;
+  p.kind = kern->kind;
+  p.d = kern->d;
+  p.square = square;
+  p.n = n;
+  p.m = square ? n : m;
+  p.npad = round_up(n, 32);
+  p.mpad = round_up(p.m, 256);
+  p.nchunks = p.npad / 32;
+  p.ks = kmm_ksteps(precision, kern->d);
+  p.tmax = tmax;
+  p.ntb = (tmax + 15) / 16;
+  p.sf = kern->outputscale;
+  p.noise = kern->noise;
+  const int64_t bpad = std::max(p.npad, p.mpad);
+  char* c = (char*)ws;
+  p.xr = c;  c += align256((size_t)bpad * p.ks * 64);
+  p.xc = c;  c += align256((size_t)p.mpad * p.ks * 64);
+  p.nrm_b = (float*)c;  c += align256((size_t)bpad * 4);
+  p.nrm_a = (float*)c;  c += align256((size_t)p.mpad * 4);
+  p.nrm64 = (double*)c; c += align256((size_t)bpad * 8);
+  const int ntb_alloc = (p.ntb + nt_launch(p.ntb) - 1) / nt_launch(p.ntb) * nt_launch(p.ntb);
+  p.vf = c;  c += align256((size_t)p.npad * ntb_alloc * 64 + 64);
+  p.part = (double*)c;
+  return true;
+}
+
+static Scale make_scale(const gp_kernel* kern) {
+  Scale s{};
+  const double c = kern->kind == GP_MATERN52 ? kMaternScale : kRbfScale;
+  for (int j = 0; j < kern->d; ++j) s.s[j] = c / kern->lengthscale[j];
+  return s;
+}
+
+static hipError_t prep_points(const KmmPlan& p, const Scale& sc, const double* P, int64_t rows,
+                              int64_t rows_pad, void* xr, void* xc, float* nr, float* nc,
+                              hipStream_t st) {
+  const int mixed = p.precision == GP_PREC_BF16X3;
+  const int thr = 256;
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(P, rows, rows_pad, p.d, sc,
+                                                                           mixed, p.nrm64);
+  const int64_t nblk = rows_pad / 16;
+  const int64_t total = nblk * p.ks * 64;
+  if (mixed) {
+    prep_frag_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
+        P, p.nrm64, rows, nblk, p.d, p.ks, sc, (bf16x8*)xr, (bf16x8*)xc);
+  } else {
+    prep_frag_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
+        P, p.nrm64, rows, nblk, p.d, p.ks, sc, (f32x4*)xr, (f32x4*)xc, nr, nc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const double* Z,
+                       hipStream_t st) {
+  const Scale sc = make_scale(kern);
+  if (p.square) {
+    // one pass gives both sides; rows up to max(npad, mpad) so xc covers mpad
+    const int64_t rows_pad = std::max(p.npad, p.mpad);
+    return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, st);
+  }
+  hipError_t e = prep_points(p, sc, X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, st);
+  if (e != hipSuccess) return e;
+  return prep_points(p, sc, Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
+}
+
+template <int KS>
+static void launch_one(bool mixed, int nt, int kind, dim3 grid, const SweepArgs& a, hipStream_t st);
+
+// BF16X3 K steps (32 wide) and FP32 K groups (16 wide) that are instantiated.
+static bool dispatch_ks(int ks, int nt, int kind, bool mixed, dim3 grid, const SweepArgs& a,
+                        hipStream_t st) {
+  if (mixed) {
+    switch (ks) {
+      case 2: launch_one<2>(true, nt, kind, grid, a, st); return true;
+      case 4: launch_one<4>(true, nt, kind, grid, a, st); return true;
+      case 5: launch_one<5>(true, nt, kind, grid, a, st); return true;
+      case 7: launch_one<7>(true, nt, kind, grid, a, st); return true;
+      case 13: launch_one<13>(true, nt, kind, grid, a, st); return true;
+      default: return false;
+    }
+  }
+  switch (ks) {
+    case 1: launch_one<1>(false, nt, kind, grid, a, st); return true;
+    case 2: launch_one<2>(false, nt, kind, grid, a, st); return true;
+    case 3: launch_one<3>(false, nt, kind, grid, a, st); return true;
+    case 4: launch_one<4>(false, nt, kind, grid, a, st); return true;
+    case 8: launch_one<8>(false, nt, kind, grid, a, st); return true;
+    default: return false;
+  }
+}
+
+template <int KS, int NT, int KIND>
+static void launch_form(bool mixed, dim3 grid, const SweepArgs& a, hipStream_t st) {
+  if constexpr (KS == 2 || KS == 4 || KS == 5 || KS == 7 || KS == 13) {
+    if (mixed) {
+      sweep_bf16x3_kernel<KS, NT, KIND><<<grid, 256, 0, st>>>(a);
+      return;
+    }
+  }
+  if constexpr (KS == 1 || KS == 2 || KS == 3 || KS == 4 || KS == 8) {
+    if (!mixed) sweep_fp32_kernel<KS, NT, KIND><<<grid, 256, 0, st>>>(a);
+  }
+}
+
+template <int KS>
+static void launch_one(bool mixed, int nt, int kind, dim3 grid, const SweepArgs& a, hipStream_t st) {
+  const bool m52 = kind == GP_MATERN52;
+  switch (nt) {
+    case 1: m52 ? launch_form<KS, 1, GP_MATERN52>(mixed, grid, a, st) : launch_form<KS, 1, GP_RBF>(mixed, grid, a, st); break;
+    case 2: m52 ? launch_form<KS, 2, GP_MATERN52>(mixed, grid, a, st) : launch_form<KS, 2, GP_RBF>(mixed, grid, a, st); break;
+    case 3: m52 ? launch_form<KS, 3, GP_MATERN52>(mixed, grid, a, st) : launch_form<KS, 3, GP_RBF>(mixed, grid, a, st); break;
+    default: m52 ? launch_form<KS, 4, GP_MATERN52>(mixed, grid, a, st) : launch_form<KS, 4, GP_RBF>(mixed, grid, a, st); break;
+  }
+}
+
+hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
+                     hipStream_t st, bool row_independent) {
+  if (t < 1 || t > p.tmax) return hipErrorInvalidValue;
+  const bool mixed = p.precision == GP_PREC_BF16X3;
+  const int ntb = (t + 15) / 16;
+  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
+  const int ntb_alloc = sc.groups * sc.nt;  // vf holds whole launch groups (zero padded)
+  const int thr = 256;
+  if (mixed) {
+    const int64_t total = p.nchunks * ntb_alloc * 64;
+    prep_v_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, p.n, t, p.nchunks,
+                                                                               ntb_alloc, (bf16x8*)p.vf);
+  } else {
+    const int64_t total = p.nchunks * ntb_alloc * 2 * 64;
+    prep_v_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, p.n, t, p.nchunks,
+                                                                             ntb_alloc, (f32x4*)p.vf);
+  }
+  SweepArgs a;
+  a.xr = p.xr;
+  a.xc = p.xc;
+  a.nrm_b = p.nrm_b;
+  a.nrm_a = p.nrm_a;
+  a.vf = p.vf;
+  a.part = p.part;
+  a.mpad = p.mpad;
+  a.nchunks = p.nchunks;
+  a.cps = sc.cps;
+  a.ntb = ntb_alloc;
+  a.tpad = sc.tpad;
+  a.square = p.square ? 1 : 0;
+  const int na = na_of(sc.nt);
+  dim3 grid((unsigned)(p.mpad / (64 * na)), (unsigned)sc.nsplit, (unsigned)sc.groups);
+  if (!dispatch_ks(p.ks, sc.nt, p.kind, mixed, grid, a, st)) return hipErrorInvalidValue;
+  const int64_t total = p.m * t;
+  kmm_epilogue_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
+      p.part, sc.nsplit, sc.tpad, p.mpad, p.m, t, p.sf, p.square ? p.sf + p.noise : 0.0,
+      p.square ? V : nullptr, ldv, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace gpk

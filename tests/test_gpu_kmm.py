@@ -1,0 +1,125 @@
+"""Parity of gp_kmm (the fused K_hat V / K(Z, X) V kernels) with the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from _helpers import col_rel_err, dev, host
+from oracle import kernel as ok
+
+pytestmark = pytest.mark.gpu
+
+# Relative error per vector ||got - ref|| / ||ref|| (the 1e-4 target; FP32 is held tighter).
+TOL = {"fp32": 2e-6, "bf16x3": 1e-4}
+# The same bound on the off-diagonal part s_f M V alone (K_hat V minus its exact diagonal).
+TOL_OFF = {"fp32": 2e-5, "bf16x3": 2e-4}
+
+
+def _run(kern_np, X, V, prec, Z=None):
+    import torch
+    from paper_2109_09817_amd import gp
+    k = gp.Kernel(kern_np.ell, kern_np.sf, kern_np.noise, "matern52" if kern_np.kind == 0 else "rbf")
+    out = gp.kmm(k, dev(X), dev(V), None if Z is None else dev(Z), precision=prec)
+    torch.cuda.synchronize()
+    return host(out)
+
+
+def _case(n, d, t, cond, seed, kind=ok.MATERN52):
+    p = synth.make_problem("c2", n=n, cond_variant=cond, kind=kind, seed=seed)
+    X = p.X[:, :d].copy()
+    ell = p.ell[:d] * (math.sqrt(d / 48.0) if cond else 1.0)
+    th = ok.Theta(ell, 1.3, 1e-3, kind)
+    V = synth.random_block(n, t, seed)
+    return X, th, V
+
+
+CASES = [
+    # n, d, t, cond-variant lengthscales
+    (2048, 32, 9, True),     # the N = 2048 workload's shape (8 probes + y)
+    (2048, 32, 9, False),
+    (4096 + 17, 48, 16, True),  # several row blocks and a ragged tail
+    (333, 7, 3, True),       # smaller than one workgroup
+    (1000, 48, 33, True),    # three 16-column blocks
+    (1, 5, 1, True),         # degenerate: one point
+]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
+@pytest.mark.parametrize("case", CASES)
+def test_square_product_matches_oracle(case, kind, prec):
+    n, d, t, cond = case
+    print(f"case n={n} d={d} t={t} cond={cond} kind={kind} prec={prec}", file=sys.stderr, flush=True)
+    X, th, V = _case(n, d, t, cond, seed=n + t, kind=kind)
+    got = _run(th, X, V, prec)
+    ref = ok.khat_matmul(X, th, V.T).T
+    err = col_rel_err(got, ref)
+    diag = (th.sf + th.noise) * V
+    err_off = col_rel_err(got - diag, ref - diag) if n > 1 else 0.0
+    print(f"  err={err:.3e} err_offdiag={err_off:.3e}", file=sys.stderr, flush=True)
+    assert err <= TOL[prec]
+    if cond and n > 1:
+        assert err_off <= TOL_OFF[prec]
+    if n == 1:
+        np.testing.assert_allclose(got, (th.sf + th.noise) * V, rtol=1e-15)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("m", [1, 155, 1000 + 3])
+def test_cross_product_matches_oracle(m, prec):
+    n, d, t = 3000, 48, 20
+    X, th, V = _case(n, d, t, True, seed=5)
+    Z = synth.query_molecule("c2", m, seed=m)[:, :d]
+    got = _run(th, X, V, prec, Z=Z)
+    ref = ok.cross_matmul(Z, X, th, V.T).T
+    # over the whole block: with m = 1 a single entry per vector can be a cancelled sum
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"cross m={m} prec={prec} err={err:.3e}", file=sys.stderr, flush=True)
+    assert err <= TOL_OFF[prec]
+
+
+def test_cross_rows_are_independent_of_the_batch():
+    # Each query row's result is bitwise the same alone and inside a larger batch.
+    n, d, t = 5000, 48, 17
+    X, th, V = _case(n, d, t, True, seed=9)
+    Z = synth.query_molecule("c2", 300, seed=3)[:, :d]
+    full = _run(th, X, V, "bf16x3", Z=Z)
+    part = _run(th, X, V, "bf16x3", Z=Z[100:137])
+    np.testing.assert_array_equal(full[:, 100:137], part)
+
+
+def test_repeat_runs_are_bitwise_identical():
+    n, d, t = 4096, 48, 16
+    X, th, V = _case(n, d, t, True, seed=2)
+    a = _run(th, X, V, "bf16x3")
+    b = _run(th, X, V, "bf16x3")
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,nrows", [("c2", 65536), ("c3d", 131072), ("c3o", 917504)])
+def test_full_size_sampled_rows(name, nrows):
+    # Full-size products (the launch configuration the benchmark times), checked on sampled rows.
+    import torch
+    from paper_2109_09817_amd import gp
+    p = synth.make_problem(name, n=nrows, cond_variant=True)
+    th = ok.Theta(p.ell, p.sf, p.noise)
+    t = 16
+    V = synth.random_block(nrows, t, 1)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    Xg, Vg = dev(p.X), dev(V)
+    rows = np.random.default_rng(0).choice(nrows, 96, replace=False)
+    rows = np.concatenate([rows, [0, nrows - 1]])
+    for prec in ("bf16x3", "fp32"):
+        out = gp.kmm(k, Xg, Vg, precision=prec)
+        torch.cuda.synchronize()
+        got = host(out)[:, rows]
+        ref = ok.khat_matmul(p.X, th, V.T, rows=rows).T
+        err = col_rel_err(got, ref)
+        diag = (th.sf + th.noise) * V[:, rows]
+        err_off = col_rel_err(got - diag, ref - diag)
+        print(f"{name} n={nrows} {prec}: err={err:.3e} off={err_off:.3e}", file=sys.stderr, flush=True)
+        assert err <= TOL[prec]
+        assert err_off <= TOL_OFF[prec]
+        del out
