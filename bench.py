@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of the BBMM hot path on one MI355X.
+
+Workload (N = 1,048,576 split into two independent models, as the paper trains
+diagonal and off-diagonal pair energies separately): n = 917,504 and
+n = 131,072 clustered MOB-ML-shaped feature rows, d = 48, Matern-5/2 ARD,
+sigma^2 = 1e-3, block [y | 15 Rademacher probes], rank-100 pivoted-Cholesky
+preconditioner, mBCG to relative residual 1e-6 (max 100 iterations).
+
+A step is one BBMM training evaluation of both models (gp_mll_and_grad:
+preconditioner, probes, mBCG with the fused K_hat V products, stochastic
+Lanczos quadrature, gradient), BF16x3 products.  `value` is the nominal
+K_hat V throughput over the whole step: sum of 2 n^2 (d + t) per product
+divided by the step wall time, inputs resident in HBM.
+
+Also reported: the tile-sweep kernel's own throughput from HIP events recorded
+on its stream (the roofline entry), mBCG iterations/s, the same step in the
+FP32 form and its agreement with the BF16x3 step, sampled-row error of the
+product against the FP64 oracle, the oracle timed on host cores on a bounded
+sample (cpu_baseline), and p50/p99 latency of a short Poisson serving run on
+the n = 262,144 serving model.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form comparison step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(row-sharding across GPUs is a design note, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_09817_amd import _lib, gp
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2109_09817_amd import build
+        build.build()
+    _lib.load()
+    dev = torch.device("cuda:0")
+
+    names = [("c3o", 917504), ("c3d", 131072)]
+    probs = {}
+    for name, n in names:
+        t0 = time.perf_counter()
+        p = synth.make_problem(name)
+        assert p.X.shape[0] == n
+        probs[name] = dict(p=p, X=torch.from_numpy(p.X).to(dev), y=torch.from_numpy(p.y).to(dev),
+                           k=gp.Kernel(p.ell, p.sf, p.noise))
+        log(f"data {name}: n={n} d={p.X.shape[1]} ({time.perf_counter() - t0:.1f}s)")
+    cfg = synth.CONFIGS["c3o"]
+    t_cols = cfg.probes + 1
+
+    def step(prec, seed):
+        out = {}
+        for name, _ in names:
+            q = probs[name]
+            r = gp.mll_and_grad(q["k"], q["X"], q["y"], probes=cfg.probes, rank=cfg.rank, max_iter=cfg.max_iter,
+                                tol=cfg.tol, seed=seed, precision=prec)
+            out[name] = r
+        return out
+
+    for w in range(args.warmup):
+        step("bf16x3", 1000 + w)
+        log(f"warmup {w} done")
+    torch.cuda.synchronize()
+    gp.profile_read(reset=True)
+    gp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for s in range(args.steps):
+        res.append(step("bf16x3", 2000 + s))
+        log(f"step {s} done: " + ", ".join(f"{k} mll={v.mll:.6g} iters={v.info['iters']}" for k, v in res[-1].items()))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = gp.profile_records()
+    launches, kms, kflops = gp.profile_read(reset=True)
+    gp.profile_enable(False)
+    # the dominant launch: the n = 917,504 square product of the 16-column block
+    big = [r for r in recs if r[0] == 917504 and r[1] == 917504]
+    big_ms = sum(r[3] for r in big) / len(big) if big else None
+    big_flops = 2.0 * 917504 * 917504 * (48 + t_cols)
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = kflops / wall / 1e12
+    kernel_tflops = big_flops / (big_ms * 1e-3) / 1e12 if big_ms else None
+    iters = sum(r.info["iters"] for st in res for r in st.values())
+    mbcg_ms = sum(r.info["ms_mbcg"] for st in res for r in st.values())
+    phases = {k: sum(r.info[k] for st in res for r in st.values()) / args.steps
+              for k in ("ms_precond", "ms_mbcg", "ms_grad")}
+
+    extra = {
+        "kmm_sweep_launches": launches,
+        "kmm_sweep_ms_all_launches": kms,
+        "kmm_sweep_tflops_all_launches": kflops / (kms * 1e-3) / 1e12 if kms > 0 else None,
+        "kmm_sweep_n917504_launches": len(big),
+        "kmm_sweep_n917504_ms_avg": big_ms,
+        "mbcg_iters_per_s": iters / (mbcg_ms * 1e-3) if mbcg_ms > 0 else None,
+        "mbcg_iters_per_step": {name: res[-1][name].info["iters"] for name, _ in names},
+        "phase_ms_per_step": phases,
+        "mll": {name: res[-1][name].mll for name, _ in names},
+    }
+
+    # the same step in the FP32 form, and its agreement with the BF16x3 step
+    if not args.no_fp32:
+        torch.cuda.synchronize()
+        gp.profile_enable(True)
+        t2 = time.perf_counter()
+        f32 = step("fp32", 2000 + args.steps - 1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        _, kms32, kfl32 = gp.profile_read(reset=True)
+        gp.profile_enable(False)
+        mixed = res[-1]
+        agree = {}
+        for name, _ in names:
+            a, b = mixed[name], f32[name]
+            g_scale = max(np.abs(b.grad).max(), 1e-300)
+            agree[name] = {
+                "mll_rel": abs(a.mll - b.mll) / abs(b.mll),
+                "quad_rel": abs(a.info["quad"] - b.info["quad"]) / abs(b.info["quad"]),
+                "grad_max_rel": float(np.max(np.abs(a.grad - b.grad) / np.maximum(np.abs(b.grad), 1e-3 * g_scale))),
+            }
+        extra["fp32_form"] = {
+            "ms_per_step": (t3 - t2) * 1e3,
+            "value_tflops": kfl32 / (t3 - t2) / 1e12,
+            "kmm_sweep_tflops_nominal": kfl32 / (kms32 * 1e-3) / 1e12 if kms32 > 0 else None,
+            "speedup_bf16x3_over_fp32": (t3 - t2) * 1e3 / ms_per_step,
+            "agreement_bf16x3_vs_fp32": agree,
+        }
+        log(f"fp32 step: {(t3 - t2) * 1e3:.0f} ms")
+
+    # sampled rows of the product against the FP64 oracle, at the full size
+    from oracle import kernel as ok
+    q = probs["c3o"]
+    p = q["p"]
+    th = ok.Theta(p.ell, p.sf, p.noise)
+    V = synth.random_block(p.X.shape[0], t_cols, 3)
+    Vg = torch.from_numpy(V).to(dev)
+    rows = np.random.default_rng(0).choice(p.X.shape[0], 64, replace=False)
+    acc = {}
+    for prec in ("bf16x3", "fp32"):
+        W = gp.kmm(q["k"], q["X"], Vg, precision=prec)
+        torch.cuda.synchronize()
+        got = W.cpu().numpy()[:, rows]
+        ref = ok.khat_matmul(p.X, th, V.T, rows=rows).T
+        diag = (th.sf + th.noise) * V[:, rows]
+        acc[prec] = {
+            "rel_err": float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))),
+            "rel_err_offdiag": float(np.max(np.linalg.norm((got - diag) - (ref - diag), axis=1)
+                                            / np.linalg.norm(ref - diag, axis=1))),
+        }
+        del W
+    extra["kmm_vs_oracle_sampled_rows"] = acc
+
+    cpu = None
+    if not args.no_cpu:
+        R = 512
+        crow = np.random.default_rng(1).choice(p.X.shape[0], R, replace=False)
+        t4 = time.perf_counter()
+        ok.khat_matmul(p.X, th, V.T, rows=crow, block=128)
+        t5 = time.perf_counter()
+        fl = 2.0 * R * p.X.shape[0] * (p.X.shape[1] + t_cols)
+        try:
+            from threadpoolctl import threadpool_info
+            blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            blas = None
+        cpu = {"value": fl / (t5 - t4) / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle K_hat V for {R} sampled rows of the n=917,504 model (t={t_cols}); "
+                         f"{t5 - t4:.1f} s; the oracle's distances (scipy cdist) run on one thread, "
+                         f"its product on {blas} BLAS threads of {os.cpu_count()} host cores"}
+        log(f"cpu baseline: {cpu['value']:.3e} TFLOP/s in {t5 - t4:.1f}s")
+
+    if not args.no_serve:
+        extra["serving"] = serve_leg(args, gp, synth, torch, dev, np)
+
+    out = {
+        "metric": "K̂·V TFLOP/s + mBCG iters/s at N=1M (mixed vs FP32, rel err 1e-4); p99 predict latency",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3 products (FP32 accumulate) / f64 solver",
+        "data": "synthetic",
+        "config": {"workload": "BBMM mll+gradient step, N=1,048,576 as two models (917,504 + 131,072 rows), "
+                               "d=48, Matern-5/2 ARD, sigma^2=1e-3, [y | 15 probes], rank-100 pivoted Cholesky, "
+                               "mBCG tol 1e-6", "n": [917504, 131072], "d": 48, "t": t_cols},
+        "roofline": {"bound": "mfma", "achieved": kernel_tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": kernel_tflops / PEAK_BF16_TFLOPS if kernel_tflops else None, "traffic": None,
+                     "kernel": "sweep_bf16x3_kernel<5,1,MATERN52> at n=917,504, t=16",
+                     "work": "2 n^2 (d + t) = 1.080e14 nominal flops per launch", "avg_launch_ms": big_ms},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_leg(args, gp, synth, torch, dev, np):
+    """Poisson requests against the resident n = 262,144 model (alpha + rank-256 variance cache)."""
+    from paper_2109_09817_amd.serve import GpuExecutor, Server, latency_summary
+    t0 = time.perf_counter()
+    p = synth.make_problem("c5")
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    X = torch.from_numpy(p.X).to(dev)
+    y = torch.from_numpy(p.y).to(dev)
+    pc = gp.pivchol(k, X, 100)
+    sol = gp.mbcg(k, X, y[None, :].contiguous(), max_iter=100, tol=1e-6, pc=pc, want_z0=False)
+    alpha = sol.U[0].contiguous()
+    t1 = time.perf_counter()
+    R, kc = gp.lanczos_cache(k, X, y, 256)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    model = gp.PredictModel(k, X, alpha, R)
+    ex = GpuExecutor(model, slots=4, max_rows=2048)
+    srv = Server(ex, d=p.X.shape[1], hbm_budget=2 << 30)
+    warm = [srv.submit(synth.query_molecule("c5", 150, seed=i)) for i in range(8)]
+    for f in warm:
+        f.result()
+    reqs = synth.request_stream(args.serve_rate, args.serve_seconds, seed=5)
+    payload = [synth.query_molecule("c5", m, seed=s) for (_, m, s) in reqs]
+    futs = []
+    start = time.perf_counter()
+    for (ta, m, s), Z in zip(reqs, payload):
+        now = time.perf_counter() - start
+        if ta > now:
+            time.sleep(ta - now)
+        futs.append(srv.submit(Z))
+    results = [f.result() for f in futs]
+    wall = time.perf_counter() - start
+    srv.close()
+    summ = latency_summary(results, wall)
+    summ.update({"model_n": p.X.shape[0], "cache_rank": kc, "rate_req_s": args.serve_rate,
+                 "seconds": args.serve_seconds, "slots": 4, "alpha_solve_iters": int(sol.alpha.shape[0]),
+                 "setup_s": {"alpha": t1 - t0, "lanczos_cache": t2 - t1}})
+    log(f"serving: p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms, {summ['requests']} requests")
+    return summ
+
+
+if __name__ == "__main__":
+    main()

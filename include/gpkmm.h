@@ -71,6 +71,7 @@ extern "C" {
 #define GP_OP_MLL 5
 #define GP_OP_PREDICT 6
 #define GP_OP_LANCZOS 7
+#define GP_OP_PREDICT_RUN 8
 
 /*
  * ARD stationary kernel with r^2 = sum_j ((x_j - z_j) / l_j)^2 (Sec. 2.2;
@@ -152,8 +153,9 @@ int gp_kmm(const gp_kernel* kern, int32_t precision,
  *   grad[j] = sum_c colw[c] * U_c^T (dK_hat / dlog theta_j) W_c
  * with dK_ab/dlog l_j = psi(r_ab) ((x_aj - x_bj)/l_j)^2, dK_hat/dlog s_f = K
  * and dK_hat/dlog sigma^2 = sigma^2 I.  Tiles are recomputed, never stored.
- * U, W: device n x t (ldu, ldw >= n); colw: host, t weights;
- * grad: host, d + 2 values.  Synchronous.
+ * U, W: device n x t with ldu = ldw = n, t <= 64, d <= 64; colw: host, t
+ * weights; grad: host, d + 2 values.  The tile products run on the FP32
+ * matrix cores for either precision value.  Synchronous.
  */
 int gp_kmm_grad(const gp_kernel* kern, int32_t precision,
                 const double* X, int64_t n,
@@ -243,13 +245,60 @@ int gp_predict(const gp_kernel* kern, int32_t precision,
                void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Prepared prediction model for serving (Eq. 1): the training-side operands of
+ * K(Z, X) [alpha | R] (the split fragments of X and of the kc + 1 columns
+ * [alpha | R]) computed once into a caller-owned device buffer `model`, so
+ * that each batch of query rows pays only for its own rows.
+ * gp_predict_model_bytes: size of `model` (0 for invalid arguments).
+ * gp_predict_prepare: fills `model` from X (device n x d), alpha (device n)
+ *   and R (device n x kc, ld n; NULL when kc = 0).  Asynchronous.
+ * gp_predict_run: mean (device m) and, when var is non-NULL and kc >= 1, the
+ *   latent variance s_f - ||K(z, X) R||^2 (device m) for query rows Z (device
+ *   m x d).  Workspace: gp_workspace_bytes(GP_OP_PREDICT_RUN, n, m, d, 0, kc,
+ *   precision).  Each row's result is bitwise independent of the other rows in
+ *   the call.  Asynchronous; `model` must stay unchanged while it is in use.
+ */
+size_t gp_predict_model_bytes(const gp_kernel* kern, int32_t precision, int64_t n, int32_t kc);
+int gp_predict_prepare(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
+                       const double* alpha, const double* R, int32_t kc,
+                       void* model, size_t model_bytes, void* stream);
+int gp_predict_run(const gp_kernel* kern, int32_t precision, const void* model, int64_t n, int32_t kc,
+                   const double* Z, int64_t m, double* mean, double* var,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_lanczos_quadrature - host utility of stochastic Lanczos quadrature:
+ * e_1^T log(T) e_1 for the J x J Lanczos tridiagonal T built from one column's
+ * CG coefficients (T_00 = 1/alpha_0, T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+ * T_j,j-1 = sqrt(beta_{j-1})/alpha_{j-1}), read as alpha[j*stride],
+ * beta[j*stride].  Returns GP_ENOTPD if T is not positive definite.
+ */
+int gp_lanczos_quadrature(const double* alpha, const double* beta, int32_t J, int32_t stride, double* out);
+
+/*
  * gp_workspace_bytes - device scratch needed by one call of `op`
- * (GP_OP_*), for n training rows, m query rows, d features, t columns
- * (probes + 1 for GP_OP_MLL: pass opts.probes), k preconditioner rank (or kc
- * for GP_OP_LANCZOS / GP_OP_PREDICT).  Returns 0 for invalid arguments.
+ * (GP_OP_*), for n training rows, m query rows (GP_OP_KMM: m = 0 for the
+ * square product), d features, t columns (GP_OP_MBCG: the block width s;
+ * GP_OP_MLL: opts.probes), k the preconditioner rank (or kc for
+ * GP_OP_LANCZOS / GP_OP_PREDICT / GP_OP_PREDICT_RUN).  Returns 0 for invalid
+ * arguments.
  */
 size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d, int32_t t,
                           int32_t k, int32_t precision);
+
+/*
+ * Kernel timing for profiling.  While enabled (process-wide), every launch of
+ * the K_hat V / K(Z, X) V tile sweep records a pair of HIP events on its own
+ * stream.  gp_profile_read waits for the recorded events and returns the
+ * number of sweep launches, their summed duration (ms) and their summed
+ * nominal flops 2 m n (d + t); reset != 0 clears the record.
+ */
+int gp_profile_enable(int32_t on);
+int gp_profile_read(int64_t* launches, double* total_ms, double* nominal_flops, int32_t reset);
+/* Per-launch view of the same record (up to cap launches, oldest first): the
+ * product's n (training rows), m (output rows), t (columns) and duration (ms);
+ * count receives the number written.  Call before a resetting gp_profile_read. */
+int gp_profile_records(int64_t cap, int64_t* n, int64_t* m, int32_t* t, double* ms, int64_t* count);
 
 /* Message of the last non-zero status returned to the calling thread. */
 const char* gp_last_error(void);

@@ -51,7 +51,7 @@ def mbcg(matmul, B: np.ndarray, precond, max_iter: int, tol: float) -> dict:
     bnorm = np.linalg.norm(B, axis=0)
     active = bnorm > 0
     iters = np.zeros(s, dtype=np.int64)
-    alphas, betas = [], []
+    alphas, betas, hist = [], [], []
     relres = np.where(bnorm > 0, 1.0, 0.0)
     for j in range(max_iter):
         if not active.any():
@@ -64,6 +64,7 @@ def mbcg(matmul, B: np.ndarray, precond, max_iter: int, tol: float) -> dict:
         iters[active] = j + 1
         rn = np.linalg.norm(R, axis=0)
         relres = np.where(active, rn / np.where(bnorm > 0, bnorm, 1.0), relres)
+        hist.append(relres.copy())
         alphas.append(a)
         active = active & ~(rn <= tol * bnorm)
         Z = precond(R)
@@ -81,6 +82,7 @@ def mbcg(matmul, B: np.ndarray, precond, max_iter: int, tol: float) -> dict:
         "iters": iters,
         "relres": relres,
         "gamma0": gamma0,
+        "relres_hist": np.array(hist).reshape(J, s),  # residual after each iteration (recording only)
     }
 
 

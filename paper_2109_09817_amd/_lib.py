@@ -28,6 +28,7 @@ GP_OP_MBCG = 4
 GP_OP_MLL = 5
 GP_OP_PREDICT = 6
 GP_OP_LANCZOS = 7
+GP_OP_PREDICT_RUN = 8
 
 
 class GpKernel(C.Structure):
@@ -77,7 +78,15 @@ PROTOTYPES = {
                                    _P, _SZ, _P]),
     "gp_predict": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _I64, _P, _P,
                              _P, _SZ, _P]),
+    "gp_predict_model_bytes": (C.c_size_t, [C.POINTER(GpKernel), _I32, _I64, _I32]),
+    "gp_predict_prepare": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _SZ, _P]),
+    "gp_predict_run": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _I32, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "gp_lanczos_quadrature": (C.c_int, [C.POINTER(_D), C.POINTER(_D), _I32, _I32, C.POINTER(_D)]),
     "gp_workspace_bytes": (C.c_size_t, [_I32, _I64, _I64, _I32, _I32, _I32, _I32]),
+    "gp_profile_enable": (C.c_int, [_I32]),
+    "gp_profile_read": (C.c_int, [C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), _I32]),
+    "gp_profile_records": (C.c_int, [_I64, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_D),
+                                     C.POINTER(_I64)]),
     "gp_last_error": (C.c_char_p, []),
     "gp_version": (C.c_char_p, []),
 }

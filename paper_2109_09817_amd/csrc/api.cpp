@@ -85,3 +85,21 @@ extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X,
   GPK_HIP(kmm_apply(p, V, ldv, t, out, ldo, st, /*row_independent=*/!square));
   return GP_OK;
 }
+
+extern "C" int gp_profile_enable(int32_t on) {
+  profile_enable(on != 0);
+  return GP_OK;
+}
+
+extern "C" int gp_profile_read(int64_t* launches, double* total_ms, double* nominal_flops, int32_t reset) {
+  if (!launches || !total_ms || !nominal_flops) return fail(GP_EINVAL, "gp_profile_read: NULL output");
+  if (profile_read(launches, total_ms, nominal_flops, reset != 0) != 0)
+    return fail(GP_EHIP, "gp_profile_read: event query failed");
+  return GP_OK;
+}
+
+extern "C" int gp_profile_records(int64_t cap, int64_t* n, int64_t* m, int32_t* t, double* ms, int64_t* count) {
+  if (cap < 0 || !n || !m || !t || !ms || !count) return fail(GP_EINVAL, "gp_profile_records: bad arguments");
+  if (profile_records(cap, n, m, t, ms, count) != 0) return fail(GP_EHIP, "gp_profile_records: event query failed");
+  return GP_OK;
+}

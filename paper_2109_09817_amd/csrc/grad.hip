@@ -1,0 +1,446 @@
+// Hyperparameter-derivative bilinear forms (the gradient of the log marginal
+// likelihood, Eq. 2, as estimated by mBCG in Sec. 3.2):
+//
+//   g_j = sum_c w_c U_c^T (dK_hat/dlog theta_j) W_c,   theta = (l_1..l_d, s_f, sigma^2)
+//
+// With C_ab = sum_c w_c U_ac W_bc and M = psi(r) (.) C,
+//   g_{l_j} = sum_ab M_ab (x~_aj - x~_bj)^2
+//           = sum_a [ x~_aj^2 sum_b M_ab + sum_b M_ab x~_bj^2 - 2 x~_aj sum_b M_ab x~_bj ]
+//   g_{s_f} = sum_ab K_ab C_ab ,   g_{sigma^2} = sigma^2 sum_c w_c U_c.W_c
+// (x~ = (x - mu) / l; the shift mu cancels in every difference and only
+// reduces rounding).  Per (16 rows a) x (32 points b) tile, all on the FP32
+// matrix cores: the distance tile (as in the K_hat V sweep), the tile of C, and
+// M times the 2d+1 columns [x~ | 1 | x~^2] of the b points; psi and the
+// kernel profile are evaluated in registers.  Tiles are recomputed, never
+// stored.  The diagonal a = b contributes only to g_{s_f} (s_f C_aa) and is
+// added exactly in FP64.
+#include <algorithm>
+#include <vector>
+
+#include "api_common.h"
+#include "solver.h"
+
+namespace gpk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kC1 = (float)M_LN2;                  // ln 2
+constexpr float kC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
+constexpr int kGradFlush = 32;
+
+// Column means of the row-major n x d matrix X (two passes, fixed order).
+__global__ void colmean_partial_kernel(const double* __restrict__ X, int64_t n, int d, int64_t rows_per_blk,
+                                       double* __restrict__ part) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
+  double s = 0.0;
+  for (int64_t i = r0; i < r1; ++i) s += X[i * d + j];
+  part[(int64_t)blockIdx.x * d + j] = s;
+}
+
+__global__ void colmean_final_kernel(const double* __restrict__ part, int64_t nblk, int d, int64_t n,
+                                     double* __restrict__ mu) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) s += part[b * d + j];
+  mu[j] = s / (double)n;
+}
+
+// float4 fragments of t columns of a column-major block, optionally weighted:
+// (blk, q, lane) -> w_c M[c*ld + p] for c = 16 q + 4 s + lane/16, p = 16 blk + lane%16.
+__global__ void prep_colfrag_kernel(const double* __restrict__ M, int64_t ld, int64_t n, int t,
+                                    const double* __restrict__ w, int64_t nblk, int KQ, f32x4* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nblk * KQ * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int q = (int)(rest % KQ);
+  const int64_t blk = rest / KQ;
+  const int64_t p = blk * 16 + (lane & 15);
+  const int g = lane >> 4;
+  f32x4 o;
+  for (int s = 0; s < 4; ++s) {
+    const int c = 16 * q + 4 * s + g;
+    o[s] = (p < n && c < t) ? (float)((w ? w[c] : 1.0) * M[(int64_t)c * ld + p]) : 0.f;
+  }
+  out[idx] = o;
+}
+
+// Fragments of the 2d+1 columns [x~ | 1 | x~^2] in the layout of the FP32
+// product's B operand: (chunk, cb, tile, lane) -> float4 over i of column
+// 16 cb + lane%16 at point 32 chunk + 16 tile + 4 (lane/16) + i.
+__global__ void prep_gv_kernel(const double* __restrict__ X, int64_t n, int d, Scale inv_ell,
+                               const double* __restrict__ mu, int64_t nchunks, int ncb, f32x4* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nchunks * ncb * 2 * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int tile = (int)(rest & 1);
+  const int64_t cbch = rest >> 1;
+  const int cb = (int)(cbch % ncb);
+  const int64_t ch = cbch / ncb;
+  const int col = 16 * cb + (lane & 15);
+  const int g = lane >> 4;
+  f32x4 o;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t b = ch * 32 + 16 * tile + 4 * g + i;
+    float v = 0.f;
+    if (b < n) {
+      if (col < d) {
+        v = (float)((X[b * d + col] - mu[col]) * inv_ell.s[col]);
+      } else if (col == d) {
+        v = 1.f;
+      } else if (col <= 2 * d) {
+        const int j = col - d - 1;
+        const double x = (X[b * d + j] - mu[j]) * inv_ell.s[j];
+        v = (float)(x * x);
+      }
+    }
+    o[i] = v;
+  }
+  out[idx] = o;
+}
+
+struct GradArgs {
+  const f32x4* xr;   // b-stream distance fragments (-2 x^)
+  const f32x4* xc;   // a-row distance fragments (x^)
+  const float* nrm_b;
+  const float* nrm_a;
+  const f32x4* wf;   // b-stream fragments of W
+  const f32x4* uf;   // a-row fragments of w (.) U
+  const f32x4* gv;   // b-stream fragments of [x~ | 1 | x~^2]
+  const double* X;
+  const double* mu;
+  Scale inv_ell;
+  int d;
+  int64_t n;
+  int64_t mpad;
+  int64_t nchunks;
+  int64_t cps;
+  double* part;      // per (block, split): d + 1 partial sums
+};
+
+template <int KQ, int KQC, int NG, int KIND>
+__global__ __launch_bounds__(256, 2) void grad_sweep_kernel(GradArgs a) {
+  __shared__ double sh_rows[4][16][NG * 16 + 1];
+  __shared__ double sh_red[4][GP_MAX_D + 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int64_t ablk = (int64_t)blockIdx.x * 4 + wave;  // one 16-row block per wave
+  const bool live = ablk * 16 < a.mpad;
+
+  f32x4 A[KQ], UA[KQC];
+  float na = 0.f;
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) A[q] = a.xc[(ablk * KQ + q) * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < KQC; ++q) UA[q] = a.uf[(ablk * KQC + q) * 64 + lane];
+    na = a.nrm_a[ablk * 16 + (lane & 15)];
+  }
+  double acc64[NG][4];
+#pragma unroll
+  for (int nb = 0; nb < NG; ++nb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc64[nb][i] = 0.0;
+  double sfsum = 0.0;
+
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cps;
+  const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
+  if (live) {
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += kGradFlush) {
+      const int64_t c1 = c0 + kGradFlush < c_end ? c0 + kGradFlush : c_end;
+      f32x4 acc[NG];
+#pragma unroll
+      for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      float sfacc = 0.f;
+      for (int64_t ch = c0; ch < c1; ++ch) {
+        f32x4 s[2], cm[2];
+#pragma unroll
+        for (int tl = 0; tl < 2; ++tl) {
+          const int64_t bblk = 2 * ch + tl;
+          s[tl] = *(const f32x4*)(a.nrm_b + bblk * 16 + 4 * g) + na;
+          cm[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) {
+            const f32x4 B = a.xr[(bblk * KQ + q) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s[tl] = __builtin_amdgcn_mfma_f32_16x16x4f32(B[e], A[q][e], s[tl], 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < KQC; ++q) {
+            const f32x4 Wb = a.wf[(bblk * KQC + q) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cm[tl] = __builtin_amdgcn_mfma_f32_16x16x4f32(Wb[e], UA[q][e], cm[tl], 0, 0, 0);
+          }
+        }
+        f32x4 Mv[2];
+#pragma unroll
+        for (int tl = 0; tl < 2; ++tl)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float m, psi;
+            if constexpr (KIND == GP_MATERN52) {
+              const float sv = __builtin_fmaxf(__builtin_fabsf(s[tl][i]), 1e-30f);
+              const float y = __builtin_amdgcn_rsqf(sv);
+              const float u0 = sv * y;
+              const float u = __builtin_fmaf(__builtin_fmaf(-u0, u0, sv), 0.5f * y, u0);
+              const float e = __builtin_amdgcn_exp2f(-u);
+              m = __builtin_fmaf(__builtin_fmaf(u, kC2, kC1), u, 1.0f) * e;
+              psi = __builtin_fmaf(u, kC1, 1.0f) * e;
+            } else {
+              m = __builtin_amdgcn_exp2f(-__builtin_fabsf(s[tl][i]));
+              psi = m;
+            }
+            const int64_t arow = ablk * 16 + (lane & 15);
+            const int64_t brow = ch * 32 + 16 * tl + 4 * g + i;
+            if (arow == brow) {
+              m = 0.f;
+              psi = 0.f;
+            }
+            sfacc = __builtin_fmaf(m, cm[tl][i], sfacc);
+            Mv[tl][i] = psi * cm[tl][i];
+          }
+        const int64_t vbase = (ch * NG) * 2 * 64 + lane;
+#pragma unroll
+        for (int nb = 0; nb < NG; ++nb) {
+          const f32x4 G0 = a.gv[vbase + (nb * 2 + 0) * 64];
+          const f32x4 G1 = a.gv[vbase + (nb * 2 + 1) * 64];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mv[0][i], G0[i], acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mv[1][i], G1[i], acc[nb], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NG; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc64[nb][i] += (double)acc[nb][i];
+      sfsum += (double)sfacc;
+    }
+  }
+  // rows of this wave: [MX (d) | rowsum | MX2 (d)] through LDS
+#pragma unroll
+  for (int nb = 0; nb < NG; ++nb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh_rows[wave][4 * g + i][16 * nb + (lane & 15)] = acc64[nb][i];
+  __syncthreads();
+  const int d = a.d;
+  double gj = 0.0;
+  if (live && lane < d) {
+    const int j = lane;
+    for (int r = 0; r < 16; ++r) {
+      const int64_t arow = ablk * 16 + r;
+      if (arow >= a.n) break;
+      const double x = (a.X[arow * d + j] - a.mu[j]) * a.inv_ell.s[j];
+      const double mx = sh_rows[wave][r][j];
+      const double rs = sh_rows[wave][r][d];
+      const double mx2 = sh_rows[wave][r][d + 1 + j];
+      gj += x * x * rs + mx2 - 2.0 * x * mx;
+    }
+  }
+  // lengthscale partials (lanes < d) and the s_f partial (all lanes) per wave
+  double sfw = sfsum;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sfw += __shfl_down(sfw, off, 64);
+  if (lane < d) sh_red[wave][lane] = gj;
+  if (lane == 0) sh_red[wave][GP_MAX_D] = live ? sfw : 0.0;
+  __syncthreads();
+  const int64_t slot = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (d + 1);
+  if (threadIdx.x < d) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += sh_red[w][threadIdx.x];
+    a.part[slot + threadIdx.x] = s;
+  } else if (threadIdx.x == 64) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += sh_red[w][GP_MAX_D];
+    a.part[slot + d] = s;
+  }
+}
+
+__global__ void grad_final_kernel(const double* __restrict__ part, int64_t nparts, int dd, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= dd) return;
+  double s = 0.0;
+  for (int64_t p = 0; p < nparts; ++p) s += part[p * dd + j];
+  out[j] = s;
+}
+
+// ------------------------------------------------------------------ host side
+
+// Column blocks of [x~ | 1 | x~^2]: sized for the instantiated K groups (d <= 16 kq),
+// so that the fragment buffer and the kernel's template agree for every d.
+static int ncb_of(int kq) { return 2 * kq + 1; }
+static int kqc_of(int t) { return (t + 15) / 16; }
+
+struct GradGeom {
+  int kq, kqc, ncb;
+  int64_t npad, mpad, nchunks, cps, nsplit, nblk_x;
+};
+
+static GradGeom grad_geom(int d, int64_t n, int t) {
+  GradGeom g;
+  g.kq = kmm_ksteps(GP_PREC_FP32, d);
+  g.kqc = kqc_of(t);
+  g.ncb = ncb_of(g.kq);
+  g.npad = (n + 31) / 32 * 32;
+  g.mpad = (n + 255) / 256 * 256;
+  g.nchunks = g.npad / 32;
+  g.nblk_x = g.mpad / 64;
+  const int64_t want = std::max<int64_t>(1, (2048 + g.nblk_x - 1) / g.nblk_x);
+  g.cps = std::max<int64_t>(2, (g.nchunks + want - 1) / want);
+  g.nsplit = (g.nchunks + g.cps - 1) / g.cps;
+  return g;
+}
+
+size_t grad_ws_bytes(int d, int64_t n, int t) {
+  const GradGeom g = grad_geom(d, n, t);
+  size_t b = kmm_plan_bytes(GP_PREC_FP32, d, n, n, true, 1);
+  b += align256((size_t)std::max(g.npad, g.mpad) * g.kqc * 64);  // W fragments
+  b += align256((size_t)g.mpad * g.kqc * 64);                    // w U fragments
+  b += align256((size_t)g.npad * g.ncb * 64);                    // [x~|1|x~^2] fragments
+  b += align256((size_t)g.nsplit * g.nblk_x * (d + 1) * 8);      // partials
+  b += align256((size_t)(d + 1) * 8);                            // reduced
+  b += align256((size_t)t * 8) + align256((size_t)d * 8);        // weights, mean
+  b += align256((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t) * 8);  // reductions
+  b += align256((size_t)t * 8);                                  // U_c . W_c
+  return b + 4096;
+}
+
+template <int KQ, int KQC, int NG>
+static void launch_grad3(int kind, dim3 grid, const GradArgs& a, hipStream_t st) {
+  if (kind == GP_MATERN52)
+    grad_sweep_kernel<KQ, KQC, NG, GP_MATERN52><<<grid, 256, 0, st>>>(a);
+  else
+    grad_sweep_kernel<KQ, KQC, NG, GP_RBF><<<grid, 256, 0, st>>>(a);
+}
+
+template <int KQ, int KQC>
+static bool launch_grad2(int ng, int kind, dim3 grid, const GradArgs& a, hipStream_t st) {
+  constexpr int NG = 2 * KQ + 1;
+  if (ng != NG) return false;
+  launch_grad3<KQ, KQC, NG>(kind, grid, a, st);
+  return true;
+}
+
+template <int KQ>
+static bool launch_grad1(int kqc, int ng, int kind, dim3 grid, const GradArgs& a, hipStream_t st) {
+  switch (kqc) {
+    case 1: return launch_grad2<KQ, 1>(ng, kind, grid, a, st);
+    case 2: return launch_grad2<KQ, 2>(ng, kind, grid, a, st);
+    case 3: return launch_grad2<KQ, 3>(ng, kind, grid, a, st);
+    case 4: return launch_grad2<KQ, 4>(ng, kind, grid, a, st);
+    default: return false;
+  }
+}
+
+int run_kmm_grad(const gp_kernel* kern, const double* X, int64_t n, const double* U, int64_t ldu, const double* W,
+                 int64_t ldw, int t, const double* colw, double* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int d = kern->d;
+  const GradGeom g = grad_geom(d, n, t);
+  const size_t kb = kmm_plan_bytes(GP_PREC_FP32, d, n, n, true, 1);
+  KmmPlan plan;
+  if (!kmm_plan_init(plan, kern, GP_PREC_FP32, n, n, true, 1, ws, kb))
+    return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace too small");
+  Carve cv((char*)ws + align256(kb), ws_bytes - align256(kb));
+  f32x4* wf = cv.take<f32x4>((size_t)std::max(g.npad, g.mpad) / 16 * g.kqc * 64);
+  f32x4* uf = cv.take<f32x4>((size_t)g.mpad / 16 * g.kqc * 64);
+  f32x4* gv = cv.take<f32x4>((size_t)g.nchunks * g.ncb * 2 * 64);
+  double* part = cv.take<double>((size_t)g.nsplit * g.nblk_x * (d + 1));
+  double* red = cv.take<double>(d + 1);
+  double* wdev = cv.take<double>(t);
+  double* mu = cv.take<double>(d);
+  double* rpart = cv.take<double>((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t));
+  double* uw = cv.take<double>(t);
+  if (!uw) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace layout failed");
+  GPK_HIP(hipMemcpyAsync(wdev, colw, sizeof(double) * t, hipMemcpyHostToDevice, st));
+  // feature means
+  {
+    const RowSplit rs = row_split(n, kDotBlocks);
+    colmean_partial_kernel<<<(unsigned)rs.nblk, 128, 0, st>>>(X, n, d, rs.rows_per_blk, rpart);
+    colmean_final_kernel<<<1, 128, 0, st>>>(rpart, rs.nblk, d, n, mu);
+  }
+  GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
+  {
+    const int64_t nbr = std::max(g.npad, g.mpad) / 16;
+    const int64_t tot = nbr * g.kqc * 64;
+    prep_colfrag_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(W, ldw, n, t, nullptr, nbr, g.kqc, wf);
+    const int64_t nba = g.mpad / 16;
+    const int64_t tot2 = nba * g.kqc * 64;
+    prep_colfrag_kernel<<<(unsigned)((tot2 + 255) / 256), 256, 0, st>>>(U, ldu, n, t, wdev, nba, g.kqc, uf);
+    Scale inv{};
+    for (int j = 0; j < d; ++j) inv.s[j] = 1.0 / kern->lengthscale[j];
+    const int64_t tot3 = g.nchunks * g.ncb * 2 * 64;
+    prep_gv_kernel<<<(unsigned)((tot3 + 255) / 256), 256, 0, st>>>(X, n, d, inv, mu, g.nchunks, g.ncb, gv);
+    GPK_HIP(hipGetLastError());
+  }
+  GradArgs a;
+  a.xr = (const f32x4*)plan.xr;
+  a.xc = (const f32x4*)plan.xc;
+  a.nrm_b = plan.nrm_b;
+  a.nrm_a = plan.nrm_a;
+  a.wf = wf;
+  a.uf = uf;
+  a.gv = gv;
+  a.X = X;
+  a.mu = mu;
+  for (int j = 0; j < d; ++j) a.inv_ell.s[j] = 1.0 / kern->lengthscale[j];
+  a.d = d;
+  a.n = n;
+  a.mpad = g.mpad;
+  a.nchunks = g.nchunks;
+  a.cps = g.cps;
+  a.part = part;
+  dim3 grid((unsigned)g.nblk_x, (unsigned)g.nsplit);
+  bool ok = false;
+  switch (g.kq) {
+    case 1: ok = launch_grad1<1>(g.kqc, g.ncb, kern->kind, grid, a, st); break;
+    case 2: ok = launch_grad1<2>(g.kqc, g.ncb, kern->kind, grid, a, st); break;
+    case 3: ok = launch_grad1<3>(g.kqc, g.ncb, kern->kind, grid, a, st); break;
+    case 4: ok = launch_grad1<4>(g.kqc, g.ncb, kern->kind, grid, a, st); break;
+    default: ok = false;
+  }
+  if (!ok) return fail(GP_EINVAL, "gp_kmm_grad: unsupported d=%d or t=%d (d <= 64, t <= 64)", d, t);
+  GPK_HIP(hipGetLastError());
+  grad_final_kernel<<<1, 256, 0, st>>>(part, g.nsplit * g.nblk_x, d + 1, red);
+  GPK_HIP(coldot(U, W, n, t, uw, rpart, st));  // requires ldu == ldw == n
+  std::vector<double> r(d + 1), uwh(t);
+  GPK_HIP(hipMemcpyAsync(r.data(), red, sizeof(double) * (d + 1), hipMemcpyDeviceToHost, st));
+  GPK_HIP(hipMemcpyAsync(uwh.data(), uw, sizeof(double) * t, hipMemcpyDeviceToHost, st));
+  GPK_HIP(hipStreamSynchronize(st));
+  double diag = 0.0;
+  for (int c = 0; c < t; ++c) diag += colw[c] * uwh[c];
+  const double sf = kern->outputscale;
+  const double psi_scale = kern->kind == GP_MATERN52 ? (5.0 / 3.0) * sf : sf;
+  for (int j = 0; j < d; ++j) grad[j] = psi_scale * r[j];
+  grad[d] = sf * (r[d] + diag);
+  grad[d + 1] = kern->noise * diag;
+  for (int j = 0; j < d + 2; ++j)
+    if (!std::isfinite(grad[j])) return fail(GP_ENONFINITE, "gp_kmm_grad: non-finite gradient entry %d", j);
+  return GP_OK;
+}
+
+}  // namespace gpk
+
+using namespace gpk;
+
+extern "C" int gp_kmm_grad(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* U,
+                           int64_t ldu, const double* W, int64_t ldw, int32_t t, const double* colw, double* grad,
+                           void* ws, size_t ws_bytes, void* stream) {
+  GPK_TRY(check_kernel(kern));
+  GPK_TRY(check_precision(precision));
+  if (!X || !U || !W || !colw || !grad) return fail(GP_EINVAL, "gp_kmm_grad: NULL argument");
+  if (n < 1) return fail(GP_EINVAL, "gp_kmm_grad: n must be >= 1");
+  if (t < 1 || t > 64) return fail(GP_EINVAL, "gp_kmm_grad: t=%d outside [1, 64]", t);
+  if (kern->d > 64) return fail(GP_EINVAL, "gp_kmm_grad: d=%d > 64 not supported", kern->d);
+  if (ldu != n || ldw != n) return fail(GP_EINVAL, "gp_kmm_grad: ldu and ldw must equal n");
+  for (int c = 0; c < t; ++c)
+    if (!std::isfinite(colw[c])) return fail(GP_EINVAL, "gp_kmm_grad: colw[%d] not finite", c);
+  GPK_TRY(check_ws(ws, ws_bytes, grad_ws_bytes(kern->d, n, t), "gp_kmm_grad"));
+  return run_kmm_grad(kern, X, n, U, ldu, W, ldw, t, colw, grad, ws, ws_bytes, (hipStream_t)stream);
+}

@@ -60,10 +60,34 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
 // Prepare the point operands (X, and Z for a cross product).
 hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const double* Z,
                        hipStream_t st);
+// Prepare only the b stream (training points) or only the output rows.
+hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, hipStream_t st);
+hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st);
+// Split V (column-major, ldv, t columns) into the plan's V fragments.
+// col0 (optional): column 0 taken from col0, columns c >= 1 from V column c - 1.
+hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, bool row_independent,
+                         hipStream_t st, const double* col0 = nullptr);
+// The sweep and epilogue on already-prepared operands (Vdiag: V for the exact
+// diagonal term of the square product, ignored for cross products).
+hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
+                     hipStream_t st, bool row_independent);
+// Bytes of the V fragments for t columns.
+size_t kmm_vfrag_bytes(int64_t n, int t);
+// A cross-product plan split in two: the training-side operands (b stream and V
+// fragments) in a long-lived `model` buffer, the query side in `ws`.
+size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax);
+size_t kmm_query_bytes(int precision, int d, int64_t n, int64_t m, int tmax);
+bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, int64_t m, int tmax, void* model,
+                    size_t model_bytes, void* ws, size_t ws_bytes);
 // out = K_hat V (square) or K(Z, X) V (cross), V column-major (ldv), t <= tmax columns.
 // Splits of the b range are chosen from n only when `row_independent` is set,
 // so that each output row's arithmetic does not depend on m.
 hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out,
                      int64_t ldo, hipStream_t st, bool row_independent = false);
+
+// Sweep timing (see gp_profile_enable / gp_profile_read).
+void profile_enable(bool on);
+int profile_read(int64_t* launches, double* total_ms, double* flops, bool reset);
+int profile_records(int64_t cap, int64_t* n, int64_t* m, int* t, double* ms, int64_t* count);
 
 }  // namespace gpk

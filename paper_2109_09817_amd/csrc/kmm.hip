@@ -32,6 +32,9 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
+#include <cmath>
 
 namespace gpk {
 
@@ -41,11 +44,10 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 // log2(e) * sqrt(5) scales x/l so that S = u^2 with u = sqrt5 r log2(e):
 // exp(-sqrt5 r) = exp2(-u) and 1 + sqrt5 r + 5r^2/3 = 1 + u ln2 + (u ln2)^2 / 3.
-constexpr double kMaternScale = 3.2259795535340955;  // sqrt(5) * log2(e)
-constexpr float kMaternC1 = 0.6931471805599453f;     // ln 2
-constexpr float kMaternC2 = 0.16015100463940034f;    // (ln 2)^2 / 3
+// (The scales are evaluated on the host from M_LOG2E; see make_scale.)
+constexpr float kMaternC1 = (float)M_LN2;                  // ln 2
+constexpr float kMaternC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
 // RBF: S = r^2 log2(e) / 2 so that exp(-r^2/2) = exp2(-S).
-constexpr double kRbfScale = 0.8493218002880191;     // sqrt(log2(e) / 2)
 
 constexpr int kFlush = 32;  // 32-point chunks accumulated in FP32 before the FP64 flush
 
@@ -193,8 +195,8 @@ __device__ __forceinline__ int vperm(int g, int j) { return j < 4 ? 4 * g + j : 
 
 // BF16X3 V fragments: (chunk, cb, hl, lane) -> 8 BF16 of V[b = 32 chunk + vperm(g, j)]
 // [c = 16 cb + lane%16], hl = 0 hi, 1 lo.
-__global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, int64_t n, int t,
-                                     int64_t nchunks, int ntb, bf16x8* __restrict__ vf) {
+__global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ col0,
+                                     int64_t n, int t, int64_t nchunks, int ntb, bf16x8* __restrict__ vf) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nchunks * ntb * 64) return;
   const int lane = (int)(idx & 63);
@@ -206,7 +208,8 @@ __global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, 
   bf16x8 hi, lo;
   for (int j = 0; j < 8; ++j) {
     const int64_t b = ch * 32 + vperm(g, j);
-    const double v = (b < n && c < t) ? V[(int64_t)c * ldv + b] : 0.0;
+    double v = 0.0;
+    if (b < n && c < t) v = col0 ? (c == 0 ? col0[b] : V[(int64_t)(c - 1) * ldv + b]) : V[(int64_t)c * ldv + b];
     const float h = bf16_round(v);
     hi[j] = (__bf16)h;
     lo[j] = (__bf16)(float)(v - (double)h);
@@ -217,8 +220,8 @@ __global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, 
 
 // FP32 V fragments: (chunk, cb, tile, lane) -> float4 of V[b = 32 chunk + 16 tile + 4g + i]
 // [c = 16 cb + lane%16], i = 0..3.
-__global__ void prep_v_fp32_kernel(const double* __restrict__ V, int64_t ldv, int64_t n, int t,
-                                   int64_t nchunks, int ntb, f32x4* __restrict__ vf) {
+__global__ void prep_v_fp32_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ col0,
+                                   int64_t n, int t, int64_t nchunks, int ntb, f32x4* __restrict__ vf) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nchunks * ntb * 2 * 64) return;
   const int lane = (int)(idx & 63);
@@ -232,7 +235,9 @@ __global__ void prep_v_fp32_kernel(const double* __restrict__ V, int64_t ldv, in
   f32x4 o;
   for (int i = 0; i < 4; ++i) {
     const int64_t b = ch * 32 + 16 * tile + 4 * g + i;
-    o[i] = (b < n && c < t) ? (float)V[(int64_t)c * ldv + b] : 0.f;
+    double v = 0.0;
+    if (b < n && c < t) v = col0 ? (c == 0 ? col0[b] : V[(int64_t)(c - 1) * ldv + b]) : V[(int64_t)c * ldv + b];
+    o[i] = (float)v;
   }
   vf[idx] = o;
 }
@@ -491,6 +496,74 @@ __global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsp
 
 // ------------------------------------------------------------------ host side
 
+// Optional timing of the tile sweeps: HIP events recorded on the sweep's own
+// stream around each launch, with the launch's nominal flops 2 m n (d + t).
+namespace {
+struct SweepTiming {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    double flops;
+    int64_t n, m;
+    int t;
+  };
+  std::vector<Rec> recs;
+};
+SweepTiming& timing() {
+  static SweepTiming t;
+  return t;
+}
+}  // namespace
+
+void profile_enable(bool on) {
+  std::lock_guard<std::mutex> g(timing().mu);
+  timing().on = on;
+}
+
+int profile_records(int64_t cap, int64_t* n, int64_t* m, int* t, double* ms, int64_t* count) {
+  std::lock_guard<std::mutex> g(timing().mu);
+  int64_t k = 0;
+  for (auto& r : timing().recs) {
+    if (k >= cap) break;
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return -1;
+    n[k] = r.n;
+    m[k] = r.m;
+    t[k] = r.t;
+    ms[k] = e;
+    ++k;
+  }
+  *count = k;
+  return 0;
+}
+
+int profile_read(int64_t* launches, double* total_ms, double* flops, bool reset) {
+  std::lock_guard<std::mutex> g(timing().mu);
+  int64_t n = 0;
+  double ms = 0.0, fl = 0.0;
+  for (auto& r : timing().recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return -1;
+    ms += e;
+    fl += r.flops;
+    ++n;
+  }
+  if (reset) {
+    for (auto& r : timing().recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    timing().recs.clear();
+  }
+  *launches = n;
+  *total_ms = ms;
+  *flops = fl;
+  return 0;
+}
+
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -596,9 +669,67 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
   return true;
 }
 
+// Model buffer: [b-stream fragments | b norms (FP32) | V fragments | FP64 norm scratch of the prepare step].
+size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax) {
+  const int ks = kmm_ksteps(precision, d);
+  if (ks < 0) return 0;
+  const int64_t npad = round_up(n, 32);
+  return align256((size_t)npad * ks * 64) + align256((size_t)npad * 4) + kmm_vfrag_bytes(n, tmax) +
+         align256((size_t)npad * 8);
+}
+
+// Query workspace: [row fragments | row norms (FP32) | FP64 norm scratch | partials].
+size_t kmm_query_bytes(int precision, int d, int64_t n, int64_t m, int tmax) {
+  const int ks = kmm_ksteps(precision, d);
+  if (ks < 0) return 0;
+  const int64_t npad = round_up(n, 32);
+  const int64_t mpad = round_up(m, 256);
+  const int ntb = (tmax + 15) / 16;
+  return align256((size_t)mpad * ks * 64) + align256((size_t)mpad * 4) + align256((size_t)mpad * 8) +
+         align256(part_bytes_max(npad, mpad, ntb, true));
+}
+
+bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, int64_t m, int tmax, void* model,
+                    size_t model_bytes, void* ws, size_t ws_bytes) {
+  if (!model || model_bytes < kmm_model_bytes(precision, kern->d, n, tmax)) return false;
+  if (m > 0 && (!ws || ws_bytes < kmm_query_bytes(precision, kern->d, n, m, tmax))) return false;
+  p.precision = precision;
+  p.kind = kern->kind;
+  p.d = kern->d;
+  p.square = false;
+  p.n = n;
+  p.m = m;
+  p.npad = round_up(n, 32);
+  p.mpad = round_up(m > 0 ? m : 1, 256);
+  p.nchunks = p.npad / 32;
+  p.ks = kmm_ksteps(precision, kern->d);
+  p.tmax = tmax;
+  p.ntb = (tmax + 15) / 16;
+  p.sf = kern->outputscale;
+  p.noise = kern->noise;
+  char* c = (char*)model;
+  p.xr = c;  c += align256((size_t)p.npad * p.ks * 64);
+  p.nrm_b = (float*)c;  c += align256((size_t)p.npad * 4);
+  p.vf = c;  c += kmm_vfrag_bytes(n, tmax);
+  if (m > 0) {
+    char* w = (char*)ws;
+    p.xc = w;  w += align256((size_t)p.mpad * p.ks * 64);
+    p.nrm_a = (float*)w;  w += align256((size_t)p.mpad * 4);
+    p.nrm64 = (double*)w;  w += align256((size_t)p.mpad * 8);
+    p.part = (double*)w;
+  } else {
+    // preparing the model only: the FP64 norm scratch lives at the end of the model buffer
+    p.xc = nullptr;
+    p.nrm_a = nullptr;
+    p.nrm64 = (double*)c;
+    p.part = nullptr;
+  }
+  return true;
+}
+
 static Scale make_scale(const gp_kernel* kern) {
   Scale s{};
-  const double c = kern->kind == GP_MATERN52 ? kMaternScale : kRbfScale;
+  const double c = kern->kind == GP_MATERN52 ? std::sqrt(5.0) * M_LOG2E : std::sqrt(0.5 * M_LOG2E);
   for (int j = 0; j < kern->d; ++j) s.s[j] = c / kern->lengthscale[j];
   return s;
 }
@@ -606,6 +737,7 @@ static Scale make_scale(const gp_kernel* kern) {
 static hipError_t prep_points(const KmmPlan& p, const Scale& sc, const double* P, int64_t rows,
                               int64_t rows_pad, void* xr, void* xc, float* nr, float* nc,
                               hipStream_t st) {
+  if (!p.nrm64 || !P || (!xr && !xc)) return hipErrorInvalidValue;
   const int mixed = p.precision == GP_PREC_BF16X3;
   const int thr = 256;
   prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(P, rows, rows_pad, p.d, sc,
@@ -630,9 +762,23 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
     const int64_t rows_pad = std::max(p.npad, p.mpad);
     return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, st);
   }
-  hipError_t e = prep_points(p, sc, X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, st);
+  hipError_t e = kmm_prepare_rows(p, kern, X, st);
   if (e != hipSuccess) return e;
-  return prep_points(p, sc, Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
+  return kmm_prepare_cols(p, kern, Z, st);
+}
+
+hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, hipStream_t st) {
+  return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, st);
+}
+
+hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st) {
+  return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
+}
+
+size_t kmm_vfrag_bytes(int64_t n, int t) {
+  const int ntb0 = (t + 15) / 16;
+  const int ntb = (ntb0 + nt_launch(ntb0) - 1) / nt_launch(ntb0) * nt_launch(ntb0);
+  return align256((size_t)round_up(n, 32) * ntb * 64 + 64);
 }
 
 template <int KS>
@@ -685,23 +831,32 @@ static void launch_one(bool mixed, int nt, int kind, dim3 grid, const SweepArgs&
   }
 }
 
-hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
-                     hipStream_t st, bool row_independent) {
-  if (t < 1 || t > p.tmax) return hipErrorInvalidValue;
-  const bool mixed = p.precision == GP_PREC_BF16X3;
+hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, bool row_independent,
+                         hipStream_t st, const double* col0) {
+  if (t < 1 || t > p.tmax || !p.vf || !V) return hipErrorInvalidValue;
   const int ntb = (t + 15) / 16;
   const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
   const int ntb_alloc = sc.groups * sc.nt;  // vf holds whole launch groups (zero padded)
   const int thr = 256;
-  if (mixed) {
+  if (p.precision == GP_PREC_BF16X3) {
     const int64_t total = p.nchunks * ntb_alloc * 64;
-    prep_v_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, p.n, t, p.nchunks,
+    prep_v_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, col0, p.n, t, p.nchunks,
                                                                                ntb_alloc, (bf16x8*)p.vf);
   } else {
     const int64_t total = p.nchunks * ntb_alloc * 2 * 64;
-    prep_v_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, p.n, t, p.nchunks,
+    prep_v_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, col0, p.n, t, p.nchunks,
                                                                              ntb_alloc, (f32x4*)p.vf);
   }
+  return hipGetLastError();
+}
+
+hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
+                     hipStream_t st, bool row_independent) {
+  if (t < 1 || t > p.tmax) return hipErrorInvalidValue;
+  if (!p.xr || !p.xc || !p.nrm_b || !p.nrm_a || !p.vf || !p.part || !out) return hipErrorInvalidValue;
+  const bool mixed = p.precision == GP_PREC_BF16X3;
+  const int ntb = (t + 15) / 16;
+  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
   SweepArgs a;
   a.xr = p.xr;
   a.xc = p.xc;
@@ -712,17 +867,47 @@ hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, doub
   a.mpad = p.mpad;
   a.nchunks = p.nchunks;
   a.cps = sc.cps;
-  a.ntb = ntb_alloc;
+  a.ntb = sc.groups * sc.nt;
   a.tpad = sc.tpad;
   a.square = p.square ? 1 : 0;
   const int na = na_of(sc.nt);
   dim3 grid((unsigned)(p.mpad / (64 * na)), (unsigned)sc.nsplit, (unsigned)sc.groups);
+  SweepTiming::Rec rec{};
+  bool timed = false;
+  {
+    std::lock_guard<std::mutex> g(timing().mu);
+    timed = timing().on;
+  }
+  if (timed) {
+    hipError_t e = hipEventCreate(&rec.a);
+    if (e == hipSuccess) e = hipEventCreate(&rec.b);
+    if (e == hipSuccess) e = hipEventRecord(rec.a, st);
+    if (e != hipSuccess) return e;
+  }
   if (!dispatch_ks(p.ks, sc.nt, p.kind, mixed, grid, a, st)) return hipErrorInvalidValue;
+  if (timed) {
+    hipError_t e = hipEventRecord(rec.b, st);
+    if (e != hipSuccess) return e;
+    rec.flops = 2.0 * (double)p.m * (double)p.n * (double)(p.d + t);
+    rec.n = p.n;
+    rec.m = p.m;
+    rec.t = t;
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().recs.push_back(rec);
+  }
+  const int thr = 256;
   const int64_t total = p.m * t;
   kmm_epilogue_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
       p.part, sc.nsplit, sc.tpad, p.mpad, p.m, t, p.sf, p.square ? p.sf + p.noise : 0.0,
-      p.square ? V : nullptr, ldv, out, ldo);
+      p.square ? Vdiag : nullptr, ldv, out, ldo);
   return hipGetLastError();
+}
+
+hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
+                     hipStream_t st, bool row_independent) {
+  hipError_t e = kmm_prepare_v(p, V, ldv, t, row_independent, st);
+  if (e != hipSuccess) return e;
+  return kmm_sweep(p, t, V, ldv, out, ldo, st, row_independent);
 }
 
 }  // namespace gpk

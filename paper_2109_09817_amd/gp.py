@@ -89,3 +89,251 @@ def kmm(kern: Kernel, X: torch.Tensor, V: torch.Tensor, Z: Optional[torch.Tensor
                           V.data_ptr(), n, t, out.data_ptr(), rows, ws.data_ptr(), ws.numel(),
                           _stream(X.device)))
     return out
+
+
+def kmm_grad(kern: Kernel, X: torch.Tensor, U: torch.Tensor, W: torch.Tensor, colw, precision="fp32") -> np.ndarray:
+    """sum_c colw[c] U_c^T (dK_hat/dlog theta) W_c for theta = (l_1..l_d, s_f, sigma^2); U, W (t, n)."""
+    lib = _lib.load()
+    n = X.shape[0]
+    t = U.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(U, "U", (t, n))
+    _need(W, "W", (t, n))
+    w = np.ascontiguousarray(np.asarray(colw, dtype=np.float64))
+    if w.shape != (t,):
+        raise ValueError("colw must have t entries")
+    g = np.zeros(kern.d + 2)
+    p = _prec(precision)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_KMM_GRAD, n, 0, kern.d, t, 0, p), X.device)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_kmm_grad(C.byref(ks), p, X.data_ptr(), n, U.data_ptr(), n, W.data_ptr(), n, t,
+                               w.ctypes.data_as(C.POINTER(C.c_double)), g.ctypes.data_as(C.POINTER(C.c_double)),
+                               ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return g
+
+
+@dataclasses.dataclass
+class Precond:
+    """Pivoted-Cholesky preconditioner P = L L^T + sigma^2 I (L: (k, n) = n x k column-major)."""
+
+    L: torch.Tensor
+    Cchol: torch.Tensor  # (k, k): row j of the tensor is column j of the lower factor
+    pivots: np.ndarray
+    rank: int
+    logdet: float
+
+    def struct(self):
+        return _lib.GpPrecond(self.L.shape[0], self.L.data_ptr(), self.Cchol.data_ptr())
+
+
+def pivchol(kern: Kernel, X: torch.Tensor, k: int) -> Precond:
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    L = torch.empty((k, n), dtype=torch.float64, device=X.device)
+    Cc = torch.empty((k, k), dtype=torch.float64, device=X.device)
+    piv = np.zeros(k, dtype=np.int64)
+    rank = C.c_int32(0)
+    ld = C.c_double(0.0)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_PIVCHOL, n, 0, kern.d, 1, k, 0), X.device)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_pivchol_precond(C.byref(ks), X.data_ptr(), n, k, L.data_ptr(), Cc.data_ptr(),
+                                      piv.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(rank), C.byref(ld),
+                                      ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return Precond(L, Cc, piv, int(rank.value), float(ld.value))
+
+
+def probe_block(y: torch.Tensor, t: int, seed: int, noise: float, pc: Optional[Precond] = None) -> torch.Tensor:
+    """[y | b_1..b_t] as a (t+1, n) tensor."""
+    lib = _lib.load()
+    n = y.shape[0]
+    _need(y, "y", (n,))
+    B = torch.empty((t + 1, n), dtype=torch.float64, device=y.device)
+    k = 0 if pc is None else pc.L.shape[0]
+    _lib.check(lib.gp_probe_block(y.data_ptr(), n, t, None if pc is None else pc.L.data_ptr(), k, noise,
+                                  C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), B.data_ptr(), _stream(y.device)))
+    return B
+
+
+@dataclasses.dataclass
+class MbcgResult:
+    U: torch.Tensor
+    Z0: Optional[torch.Tensor]
+    alpha: np.ndarray  # (iters, s)
+    beta: np.ndarray
+    iters: np.ndarray
+    relres: np.ndarray
+    gamma0: np.ndarray
+    status: int
+
+
+def mbcg(kern: Kernel, X: torch.Tensor, B: torch.Tensor, max_iter: int, tol: float,
+         pc: Optional[Precond] = None, precision="bf16x3", want_z0: bool = True) -> MbcgResult:
+    lib = _lib.load()
+    n = X.shape[0]
+    s = B.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(B, "B", (s, n))
+    U = torch.empty_like(B)
+    Z0 = torch.empty_like(B) if want_z0 else None
+    al = np.zeros((max_iter, s))
+    be = np.zeros((max_iter, s))
+    it = np.zeros(s, dtype=np.int32)
+    rr = np.zeros(s)
+    g0 = np.zeros(s)
+    dp = C.POINTER(C.c_double)
+    out = _lib.GpMbcgOut(al.ctypes.data_as(dp), be.ctypes.data_as(dp), it.ctypes.data_as(C.POINTER(C.c_int32)),
+                         rr.ctypes.data_as(dp), g0.ctypes.data_as(dp), 0)
+    p = _prec(precision)
+    k = 0 if pc is None else pc.L.shape[0]
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_MBCG, n, 0, kern.d, s, k, p), X.device)
+    ks, _keep = kern.struct()
+    pcs = pc.struct() if pc is not None else None
+    rc = _lib.check(lib.gp_mbcg(C.byref(ks), p, X.data_ptr(), n, None if pcs is None else C.byref(pcs),
+                                B.data_ptr(), s, max_iter, tol, U.data_ptr(), _ptr(Z0), C.byref(out),
+                                ws.data_ptr(), ws.numel(), _stream(X.device)))
+    J = out.total_iters
+    return MbcgResult(U, Z0, al[:J].copy(), be[:J].copy(), it, rr, g0, rc)
+
+
+@dataclasses.dataclass
+class MllResult:
+    mll: float
+    grad: Optional[np.ndarray]
+    info: dict
+    status: int
+
+
+def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, probes: int, rank: int, max_iter: int,
+                 tol: float, seed: int, precision="bf16x3", with_grad: bool = True) -> MllResult:
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(y, "y", (n,))
+    p = _prec(precision)
+    opts = _lib.GpMllOpts(probes, rank, max_iter, p, tol, C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF))
+    info = _lib.GpMllInfo()
+    mll = C.c_double(0.0)
+    g = np.zeros(kern.d + 2)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_MLL, n, 0, kern.d, probes, rank, p), X.device)
+    ks, _keep = kern.struct()
+    rc = _lib.check(lib.gp_mll_and_grad(C.byref(ks), C.byref(opts), X.data_ptr(), y.data_ptr(), n, C.byref(mll),
+                                        g.ctypes.data_as(C.POINTER(C.c_double)) if with_grad else None,
+                                        C.byref(info), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    inf = {f: getattr(info, f) for f, _ in _lib.GpMllInfo._fields_}
+    return MllResult(float(mll.value), g if with_grad else None, inf, rc)
+
+
+def lanczos_cache(kern: Kernel, X: torch.Tensor, y: torch.Tensor, kc: int, precision="bf16x3"):
+    """Variance cache R (kc, n) with R R^T ~ K_hat^{-1} on the Krylov space of y; returns (R, rank)."""
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(y, "y", (n,))
+    R = torch.empty((kc, n), dtype=torch.float64, device=X.device)
+    p = _prec(precision)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_LANCZOS, n, 0, kern.d, 1, kc, p), X.device)
+    kout = C.c_int32(0)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_lanczos_cache(C.byref(ks), p, X.data_ptr(), y.data_ptr(), n, kc, R.data_ptr(),
+                                    C.byref(kout), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return R, int(kout.value)
+
+
+class PredictModel:
+    """A trained model kept resident on the GPU: prepared operands of K(., X) [alpha | R]."""
+
+    def __init__(self, kern: Kernel, X: torch.Tensor, alpha: torch.Tensor, R: Optional[torch.Tensor] = None,
+                 precision="bf16x3"):
+        lib = _lib.load()
+        self.kern = kern
+        self.n = X.shape[0]
+        _need(X, "X", (self.n, kern.d))
+        _need(alpha, "alpha", (self.n,))
+        self.kc = 0 if R is None else R.shape[0]
+        if R is not None:
+            _need(R, "R", (self.kc, self.n))
+        self.precision = _prec(precision)
+        self.device = X.device
+        ks, self._ell = kern.struct()
+        self._ks = ks
+        nb = lib.gp_predict_model_bytes(C.byref(ks), self.precision, self.n, self.kc)
+        if nb == 0:
+            raise ValueError("invalid prediction model arguments")
+        self.model = workspace(nb, X.device)
+        _lib.check(lib.gp_predict_prepare(C.byref(ks), self.precision, X.data_ptr(), self.n, alpha.data_ptr(),
+                                          _ptr(R), self.kc, self.model.data_ptr(), self.model.numel(),
+                                          _stream(X.device)))
+
+    def workspace_bytes(self, m: int) -> int:
+        return _lib.load().gp_workspace_bytes(_lib.GP_OP_PREDICT_RUN, self.n, m, self.kern.d, 0, self.kc,
+                                              self.precision)
+
+    def __call__(self, Z: torch.Tensor, with_var: bool = True, ws: Optional[torch.Tensor] = None,
+                 mean: Optional[torch.Tensor] = None, var: Optional[torch.Tensor] = None, stream=None):
+        lib = _lib.load()
+        m = Z.shape[0]
+        _need(Z, "Z", (m, self.kern.d))
+        if mean is None:
+            mean = torch.empty(m, dtype=torch.float64, device=self.device)
+        if with_var and self.kc > 0 and var is None:
+            var = torch.empty(m, dtype=torch.float64, device=self.device)
+        if not with_var or self.kc == 0:
+            var = None
+        need = self.workspace_bytes(m)
+        if ws is None or ws.numel() < need:
+            ws = workspace(need, self.device)
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        _lib.check(lib.gp_predict_run(C.byref(self._ks), self.precision, self.model.data_ptr(), self.n, self.kc,
+                                      Z.data_ptr(), m, mean.data_ptr(), _ptr(var), ws.data_ptr(), ws.numel(), st))
+        return mean, var
+
+
+def predict(kern: Kernel, X: torch.Tensor, alpha: torch.Tensor, Z: torch.Tensor, R: Optional[torch.Tensor] = None,
+            precision="bf16x3"):
+    """One-shot predictive mean (and variance when a cache R is given) at query rows Z."""
+    lib = _lib.load()
+    n = X.shape[0]
+    m = Z.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(alpha, "alpha", (n,))
+    _need(Z, "Z", (m, kern.d))
+    kc = 0 if R is None else R.shape[0]
+    if R is not None:
+        _need(R, "R", (kc, n))
+    p = _prec(precision)
+    mean = torch.empty(m, dtype=torch.float64, device=X.device)
+    var = torch.empty(m, dtype=torch.float64, device=X.device) if kc > 0 else None
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_PREDICT, n, m, kern.d, 0, kc, p), X.device)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_predict(C.byref(ks), p, X.data_ptr(), n, alpha.data_ptr(), _ptr(R), kc, Z.data_ptr(), m,
+                              mean.data_ptr(), _ptr(var), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return mean, var
+
+
+def profile_enable(on: bool = True) -> None:
+    _lib.check(_lib.load().gp_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True):
+    """(launches, total_ms, nominal_flops) of the timed tile sweeps since the last reset."""
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    fl = C.c_double(0.0)
+    _lib.check(_lib.load().gp_profile_read(C.byref(n), C.byref(ms), C.byref(fl), 1 if reset else 0))
+    return int(n.value), float(ms.value), float(fl.value)
+
+
+def profile_records(cap: int = 4096):
+    """Per-launch (n, m, t, ms) records of the timed tile sweeps (oldest first)."""
+    n = np.zeros(cap, dtype=np.int64)
+    m = np.zeros(cap, dtype=np.int64)
+    t = np.zeros(cap, dtype=np.int32)
+    ms = np.zeros(cap)
+    cnt = C.c_int64(0)
+    _lib.check(_lib.load().gp_profile_records(cap, n.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              m.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              ms.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)))
+    k = int(cnt.value)
+    return [(int(n[i]), int(m[i]), int(t[i]), float(ms[i])) for i in range(k)]
