@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--profile-kmm", type=int, default=0, metavar="K",
+                    help="profiling mode: a 1 GiB device copy (traffic calibration) then K products "
+                         "K_hat V at n = 917,504, t = 16 (BF16x3), and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -69,6 +72,10 @@ def main():
         build.build()
     _lib.load()
     dev = torch.device("cuda:0")
+
+    if args.profile_kmm:
+        profile_kmm(args, gp, synth, torch, dev)
+        return
 
     names = [("c3o", 917504), ("c3d", 131072)]
     probs = {}
@@ -231,6 +238,27 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def profile_kmm(args, gp, synth, torch, dev):
+    """Kernels to read hardware counters on: one plain copy of known size, then K products."""
+    p = synth.make_problem("c3o")
+    X = torch.from_numpy(p.X).to(dev)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    V = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 3)).to(dev)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    out = torch.empty_like(V)
+    gp.profile_enable(True)
+    for _ in range(args.profile_kmm):
+        gp.kmm(k, X, V, precision="bf16x3", out=out)
+    torch.cuda.synchronize()
+    recs = gp.profile_records()
+    gp.profile_read(reset=True)
+    print(json.dumps({"profile_kmm": {"copy_bytes": 2 * a.numel() * 8, "launch_ms": [r[3] for r in recs]}}),
+          flush=True)
 
 
 def serve_leg(args, gp, synth, torch, dev, np):

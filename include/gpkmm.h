@@ -154,8 +154,9 @@ int gp_kmm(const gp_kernel* kern, int32_t precision,
  * with dK_ab/dlog l_j = psi(r_ab) ((x_aj - x_bj)/l_j)^2, dK_hat/dlog s_f = K
  * and dK_hat/dlog sigma^2 = sigma^2 I.  Tiles are recomputed, never stored.
  * U, W: device n x t with ldu = ldw = n, t <= 64, d <= 64; colw: host, t
- * weights; grad: host, d + 2 values.  The tile products run on the FP32
- * matrix cores for either precision value.  Synchronous.
+ * weights; grad: host, d + 2 values.  precision selects the matrix-core form
+ * of the tile products (distances, C = U diag(w) W^T and psi (.) C times
+ * [x~ | 1 | x~^2]) as for gp_kmm.  Synchronous.
  */
 int gp_kmm_grad(const gp_kernel* kern, int32_t precision,
                 const double* X, int64_t n,

@@ -12,7 +12,7 @@ namespace gpk {
 size_t pivchol_ws_bytes(int64_t n, int k);
 size_t mbcg_ws_bytes(int precision, int d, int64_t n, int s, int rank);
 size_t mll_ws_bytes(int precision, int d, int64_t n, int t, int k);
-size_t grad_ws_bytes(int d, int64_t n, int t);
+size_t grad_ws_bytes(int precision, int d, int64_t n, int t);
 
 constexpr int kMaxCache = 4095;  // kc + 1 <= 4096 product columns
 
@@ -179,7 +179,7 @@ extern "C" size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d
       return kmm_plan_bytes(precision, d, n, m > 0 ? m : n, m <= 0, t);
     case GP_OP_KMM_GRAD:
       if (t < 1 || t > 64 || d > 64) return 0;
-      return grad_ws_bytes(d, n, t);
+      return grad_ws_bytes(precision, d, n, t);
     case GP_OP_PIVCHOL:
       if (k < 1) return 0;
       return pivchol_ws_bytes(n, k);

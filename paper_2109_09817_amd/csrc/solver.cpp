@@ -291,9 +291,10 @@ extern "C" int gp_mbcg(const gp_kernel* kern, int32_t precision, const double* X
 // ------------------------------------------------------------ mll and gradient
 
 namespace gpk {
-size_t grad_ws_bytes(int d, int64_t n, int t);
-int run_kmm_grad(const gp_kernel* kern, const double* X, int64_t n, const double* U, int64_t ldu, const double* W,
-                 int64_t ldw, int t, const double* colw, double* grad, void* ws, size_t ws_bytes, hipStream_t st);
+size_t grad_ws_bytes(int precision, int d, int64_t n, int t);
+int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t n, const double* U, int64_t ldu,
+                 const double* W, int64_t ldw, int t, const double* colw, double* grad, void* ws, size_t ws_bytes,
+                 hipStream_t st);
 
 size_t mll_ws_bytes(int precision, int d, int64_t n, int t, int k) {
   const int s = t + 1;
@@ -304,7 +305,7 @@ size_t mll_ws_bytes(int precision, int d, int64_t n, int t, int k) {
   b += align256(16 * 8);                             // quad
   size_t inner = mbcg_ws_bytes(precision, d, n, s, k);
   if (k > 0) inner = std::max(inner, pivchol_ws_bytes(n, k));
-  inner = std::max(inner, grad_ws_bytes(d, n, s));
+  inner = std::max(inner, grad_ws_bytes(precision, d, n, s));
   inner = std::max(inner, (size_t)row_split(n, kDotBlocks).nblk * 8 + 256);
   return b + inner + 4096;
 }
@@ -376,7 +377,7 @@ extern "C" int gp_mll_and_grad(const gp_kernel* kern, const gp_mll_opts* opts, c
     GPK_HIP(launch_copy(U, Z0, n, st));
     std::vector<double> w(s, -0.5 / t);
     w[0] = 0.5;
-    GPK_TRY(run_kmm_grad(kern, X, n, U, n, Z0, n, s, w.data(), grad, inner, inner_bytes, st));
+    GPK_TRY(run_kmm_grad(kern, opts->precision, X, n, U, n, Z0, n, s, w.data(), grad, inner, inner_bytes, st));
   }
   const double t4 = now_ms();
   if (info) {
