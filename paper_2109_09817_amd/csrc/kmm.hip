@@ -264,14 +264,47 @@ struct NAOf {
   static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
 };
 
+// Split 8 FP32 values into BF16 hi = RNE(m) and lo = RNE(m - hi), two values per
+// v_cvt_pk_bf16_f32; hi is widened back with one shift or mask per value.
+__device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& L) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const f32x2 v = {m[2 * p], m[2 * p + 1]};
+    const bf16x2 h = __builtin_convertvector(v, bf16x2);
+    const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+    const float h0 = __builtin_bit_cast(float, hb << 16);
+    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+    const f32x2 r = {v[0] - h0, v[1] - h1};
+    const bf16x2 l = __builtin_convertvector(r, bf16x2);
+    H[2 * p] = h[0];
+    H[2 * p + 1] = h[1];
+    L[2 * p] = l[0];
+    L[2 * p + 1] = l[1];
+  }
+}
+
+// One 32-point chunk of the b stream staged in LDS: the 2 KS point fragments
+// followed by the NT (hi, lo) V fragments, 64 lanes x 16 bytes each.
+template <int KS, int NT>
+struct ChunkUnits {
+  static constexpr int kPoint = 2 * KS * 64;
+  static constexpr int kV = 2 * NT * 64;
+  static constexpr int kAll = kPoint + kV;
+  static constexpr int kPerThread = (kAll + 255) / 256;
+};
+
 template <int KS, int NT, int KIND>
 __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
   constexpr int NA = NAOf<NT>::value;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  using CU = ChunkUnits<KS, NT>;
+  __shared__ bf16x8 stage[2][CU::kAll];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int g = lane >> 4;
-  const int64_t ablk0 = ((int64_t)blockIdx.x * 4 + wave) * NA;
-  if (ablk0 * 16 >= a.mpad) return;
+  const int64_t ablk0 = ((int64_t)blockIdx.x * 4 + wave) * NA;  // every wave is live: mpad % (64 NA) == 0
   const int cb0 = blockIdx.z * NT;
   const bf16x8* __restrict__ xr = (const bf16x8*)a.xr;
   const bf16x8* __restrict__ xc = (const bf16x8*)a.xc;
@@ -284,76 +317,104 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
     for (int ks = 0; ks < KS; ++ks) A[ab][ks] = xc[((ablk0 + ab) * KS + ks) * 64 + lane];
 
   double acc64[NA][NT][4];
+  f32x4 acc[NA][NT];
 #pragma unroll
   for (int ab = 0; ab < NA; ++ab)
 #pragma unroll
-    for (int cb = 0; cb < NT; ++cb)
+    for (int cb = 0; cb < NT; ++cb) {
+      acc[ab][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc64[ab][cb][i] = 0.0;
+    }
 
   const int64_t c_begin = (int64_t)blockIdx.y * a.cps;
   const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
-  for (int64_t c0 = c_begin; c0 < c_end; c0 += kFlush) {
-    const int64_t c1 = c0 + kFlush < c_end ? c0 + kFlush : c_end;
-    f32x4 acc[NA][NT];
+
+  // cooperative load of one chunk: unit u < kPoint comes from the point stream,
+  // the rest from the V fragments of this launch's column group
+  bf16x8 pre[CU::kPerThread];
+  auto fetch = [&](int64_t ch) {
 #pragma unroll
-    for (int ab = 0; ab < NA; ++ab)
-#pragma unroll
-      for (int cb = 0; cb < NT; ++cb) acc[ab][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t ch = c0; ch < c1; ++ch) {
-      bf16x8 B0[KS], B1[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        B0[ks] = xr[((2 * ch) * KS + ks) * 64 + lane];
-        B1[ks] = xr[((2 * ch + 1) * KS + ks) * 64 + lane];
-      }
-      bf16x8 VH[NT], VL[NT];
-#pragma unroll
-      for (int cb = 0; cb < NT; ++cb) {
-        const int64_t base = ((ch * a.ntb + cb0 + cb) * 2) * 64 + lane;
-        VH[cb] = vf[base];
-        VL[cb] = vf[base + 64];
-      }
-#pragma unroll
-      for (int ab = 0; ab < NA; ++ab) {
-        f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
-          s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
-        }
-        f32x8 mv;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          mv[i] = profile<KIND, false>(s0[i]);
-          mv[4 + i] = profile<KIND, false>(s1[i]);
-        }
-        if (a.square) {
-          const int64_t arow = (ablk0 + ab) * 16;
-          if (arow == ch * 32 || arow == ch * 32 + 16) {
-            const int off = arow == ch * 32 ? 0 : 4;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if ((lane & 15) == 4 * g + i) mv[off + i] = 0.f;
-          }
-        }
-        const bf16x8 H = __builtin_convertvector(mv, bf16x8);
-        const f32x8 hf = __builtin_convertvector(H, f32x8);
-        const bf16x8 L = __builtin_convertvector(mv - hf, bf16x8);
-#pragma unroll
-        for (int cb = 0; cb < NT; ++cb) {
-          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VH[cb], acc[ab][cb], 0, 0, 0);
-          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VL[cb], acc[ab][cb], 0, 0, 0);
-          acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, VH[cb], acc[ab][cb], 0, 0, 0);
-        }
+    for (int r = 0; r < CU::kPerThread; ++r) {
+      const int u = tid + 256 * r;
+      if (u < CU::kPoint) {
+        pre[r] = xr[(2 * ch * KS) * 64 + u];
+      } else if (u < CU::kAll) {
+        pre[r] = vf[(ch * a.ntb + cb0) * 2 * 64 + (u - CU::kPoint)];
       }
     }
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int ab = 0; ab < NA; ++ab)
+    for (int r = 0; r < CU::kPerThread; ++r) {
+      const int u = tid + 256 * r;
+      if (u < CU::kAll) stage[buf][u] = pre[r];
+    }
+  };
+  if (c_begin < c_end) {
+    fetch(c_begin);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t ch = c_begin; ch < c_end; ++ch) {
+    const int cur = (int)((ch - c_begin) & 1);
+    const bool more = ch + 1 < c_end;
+    if (more) fetch(ch + 1);
+    bf16x8 B0[KS], B1[KS], VH[NT], VL[NT];
 #pragma unroll
-      for (int cb = 0; cb < NT; ++cb)
+    for (int ks = 0; ks < KS; ++ks) {
+      B0[ks] = stage[cur][ks * 64 + lane];
+      B1[ks] = stage[cur][(KS + ks) * 64 + lane];
+    }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc64[ab][cb][i] += (double)acc[ab][cb][i];
+    for (int cb = 0; cb < NT; ++cb) {
+      VH[cb] = stage[cur][CU::kPoint + (2 * cb) * 64 + lane];
+      VL[cb] = stage[cur][CU::kPoint + (2 * cb + 1) * 64 + lane];
+    }
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab) {
+      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
+        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
+      }
+      f32x8 mv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mv[i] = profile<KIND, false>(s0[i]);
+        mv[4 + i] = profile<KIND, false>(s1[i]);
+      }
+      if (a.square) {
+        const int64_t arow = (ablk0 + ab) * 16;
+        if (arow == ch * 32 || arow == ch * 32 + 16) {
+          const int off = arow == ch * 32 ? 0 : 4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if ((lane & 15) == 4 * g + i) mv[off + i] = 0.f;
+        }
+      }
+      bf16x8 H, L;
+      split_bf16x8(mv, H, L);
+#pragma unroll
+      for (int cb = 0; cb < NT; ++cb) {
+        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VH[cb], acc[ab][cb], 0, 0, 0);
+        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VL[cb], acc[ab][cb], 0, 0, 0);
+        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, VH[cb], acc[ab][cb], 0, 0, 0);
+      }
+    }
+    if (((ch - c_begin + 1) % kFlush) == 0 || !more) {
+#pragma unroll
+      for (int ab = 0; ab < NA; ++ab)
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc64[ab][cb][i] += (double)acc[ab][cb][i];
+          acc[ab][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
   }
   // partial[(split * tpad + col) * mpad + row]
 #pragma unroll
