@@ -8,24 +8,23 @@
 //           = sum_a [ x~_aj^2 sum_b M_ab + sum_b M_ab x~_bj^2 - 2 x~_aj sum_b M_ab x~_bj ]
 //   g_{s_f} = sum_ab K_ab C_ab ,   g_{sigma^2} = sigma^2 sum_c w_c U_c.W_c
 // (x~ = (x - mu) / l; the shift mu cancels in every difference and only
-// reduces rounding).  Per (16 rows a) x (32 points b) tile, all on the FP32
-// matrix cores: the distance tile (as in the K_hat V sweep), the tile of C, and
-// M times the 2d+1 columns [x~ | 1 | x~^2] of the b points; psi and the
-// kernel profile are evaluated in registers.  Tiles are recomputed, never
-// stored.  The diagonal a = b contributes only to g_{s_f} (s_f C_aa) and is
-// added exactly in FP64.
+// reduces rounding).  Tiles are recomputed, never stored.  The diagonal a = b
+// contributes only to g_{s_f} (s_f C_aa) and is added exactly in FP64.
+//
+// FP32 form: every (16 rows a) x (32 points b) tile of the full matrix on the
+// FP32 matrix cores: the distance tile (as in the K_hat V sweep), the tile of
+// C, and M times the 2d+1 columns [x~ | 1 | x~^2] of the b points.
+// BF16X3 form: the pairs a < b only, with the symmetric part of C (grad_tri.h).
 #include <algorithm>
 #include <vector>
 
 #include "api_common.h"
+#include "grad_tri.h"
+#include "mfma_bf16.h"
 #include "solver.h"
 
 namespace gpk {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr float kC1 = (float)M_LN2;                  // ln 2
-constexpr float kC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
 constexpr int kGradFlush = 32;
 
 // Column means of the row-major n x d matrix X (two passes, fixed order).
@@ -190,8 +189,8 @@ __global__ __launch_bounds__(256, 2) void grad_sweep_kernel(GradArgs a) {
               const float u0 = sv * y;
               const float u = __builtin_fmaf(__builtin_fmaf(-u0, u0, sv), 0.5f * y, u0);
               const float e = __builtin_amdgcn_exp2f(-u);
-              m = __builtin_fmaf(__builtin_fmaf(u, kC2, kC1), u, 1.0f) * e;
-              psi = __builtin_fmaf(u, kC1, 1.0f) * e;
+              m = __builtin_fmaf(__builtin_fmaf(u, kMaternC2, kMaternC1), u, 1.0f) * e;
+              psi = __builtin_fmaf(u, kMaternC1, 1.0f) * e;
             } else {
               m = __builtin_amdgcn_exp2f(-__builtin_fabsf(s[tl][i]));
               psi = m;
@@ -274,75 +273,68 @@ __global__ void grad_final_kernel(const double* __restrict__ part, int64_t npart
 // ------------------------------------------------------------------ host side
 
 // ------------------------------------------------------------ BF16X3 form
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
+//
+// The BF16X3 form runs the upper-triangle sweep of grad_tri.h: every unordered
+// pair once, with the symmetric part of C.
 
 __device__ __forceinline__ float bf16r(double x) { return (float)(__bf16)(float)x; }
 
-// Point order of the M . G product's K index inside a 32-point chunk (where the two
-// distance tiles' accumulators leave the points; the same permutation as the
-// K_hat V sweep).
-__device__ __forceinline__ int gperm(int g, int j) { return j < 4 ? 4 * g + j : 12 + 4 * g + j; }
-
-// BF16X3 fragments of t columns of a column-major block (optionally weighted), with
-// the K index 3t long: rows role (A operand) [hi | hi | lo], columns role (B
-// operand) [hi | lo | hi], so that sum_K A B = hi.hi + hi.lo + lo.hi over the t columns.
-__global__ void prep_matfrag_bf16x3_kernel(const double* __restrict__ M, int64_t ld, int64_t n, int t,
-                                           const double* __restrict__ w, int64_t nblk, int KS, int cols_role,
-                                           bf16x8* __restrict__ out) {
+// BF16X3 fragments of the 2t columns [M1 | M2] (weighted by w when given), K
+// index 6t long.  A-operand role: [hi | hi | lo]; B-operand role: [hi | lo | hi],
+// so that sum_K A B = hi.hi + hi.lo + lo.hi over the 2t columns.  Fragment
+// (blk, q, lane) holds K = 32 q + 8 (lane/16) + j of point 16 blk + lane%16.
+__global__ void prep_pairfrag_bf16x3_kernel(const double* __restrict__ M1, const double* __restrict__ M2,
+                                            int64_t ld, int64_t n, int t, const double* __restrict__ w,
+                                            int64_t nblk, int KSC, int b_role, bf16x8* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nblk * KS * 64) return;
+  if (idx >= nblk * KSC * 64) return;
   const int lane = (int)(idx & 63);
   const int64_t rest = idx >> 6;
-  const int ks = (int)(rest % KS);
-  const int64_t blk = rest / KS;
+  const int q = (int)(rest % KSC);
+  const int64_t blk = rest / KSC;
   const int64_t p = blk * 16 + (lane & 15);
   const int g = lane >> 4;
   bf16x8 o;
   for (int j = 0; j < 8; ++j) {
-    const int k = 32 * ks + 8 * g + j;
+    const int k = 32 * q + 8 * g + j;
     float v = 0.f;
-    if (p < n && k < 3 * t) {
-      const int seg = k / t, c = k - seg * t;
+    if (p < n && k < 6 * t) {
+      const int seg = k / (2 * t), cc = k - seg * 2 * t;
+      const int c = cc < t ? cc : cc - t;
+      const double* M = cc < t ? M1 : M2;
       const double x = (w ? w[c] : 1.0) * M[(int64_t)c * ld + p];
       const float h = bf16r(x);
       const float l = bf16r(x - (double)h);
-      v = cols_role ? (seg == 1 ? l : h) : (seg == 2 ? l : h);
+      v = b_role ? (seg == 1 ? l : h) : (seg == 2 ? l : h);
     }
     o[j] = (__bf16)v;
   }
   out[idx] = o;
 }
 
-// BF16X3 fragments of [x~ | 1 | x~^2] in the B-operand layout of the M . G product:
-// (chunk, cb, hl, lane) -> 8 BF16 (hi or lo) of column 16 cb + lane%16 at the points
-// 32 chunk + gperm(lane/16, j).
-__global__ void prep_gv_bf16x3_kernel(const double* __restrict__ X, int64_t n, int d, Scale inv_ell,
-                                      const double* __restrict__ mu, int64_t nchunks, int ncb,
-                                      bf16x8* __restrict__ out) {
+// BF16X3 fragments of the 2 NJ column blocks [x~ | x~^2] (each d columns padded
+// to 16 NJ) in the B-operand layout of the forms product: (chunk, cb, hl, lane)
+// -> 8 BF16 (hi or lo) of column 16 cb + lane%16 at the points 32 chunk + vperm(lane/16, j).
+__global__ void prep_formfrag_bf16x3_kernel(const double* __restrict__ X, int64_t n, int d, int nj,
+                                            const double* __restrict__ inv_ell, const double* __restrict__ mu,
+                                            int64_t nchunks, bf16x8* __restrict__ out) {
+  const int ng = 2 * nj;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nchunks * ncb * 64) return;
+  if (idx >= nchunks * ng * 64) return;
   const int lane = (int)(idx & 63);
-  const int64_t rest = idx >> 6;  // ch * ncb + cb
-  const int cb = (int)(rest % ncb);
-  const int64_t ch = rest / ncb;
-  const int col = 16 * cb + (lane & 15);
+  const int64_t rest = idx >> 6;  // ch * ng + cb
+  const int cb = (int)(rest % ng);
+  const int64_t ch = rest / ng;
+  const bool square = cb >= nj;
+  const int jj = 16 * (square ? cb - nj : cb) + (lane & 15);
   const int g = lane >> 4;
   bf16x8 hi, lo;
   for (int j = 0; j < 8; ++j) {
-    const int64_t b = ch * 32 + gperm(g, j);
+    const int64_t b = ch * 32 + vperm(g, j);
     double v = 0.0;
-    if (b < n) {
-      if (col < d) {
-        v = (X[b * d + col] - mu[col]) * inv_ell.s[col];
-      } else if (col == d) {
-        v = 1.0;
-      } else if (col <= 2 * d) {
-        const int jj = col - d - 1;
-        const double x = (X[b * d + jj] - mu[jj]) * inv_ell.s[jj];
-        v = x * x;
-      }
+    if (b < n && jj < d) {
+      const double x = (X[b * d + jj] - mu[jj]) * inv_ell[jj];
+      v = square ? x * x : x;
     }
     const float h = bf16r(v);
     hi[j] = (__bf16)h;
@@ -352,192 +344,98 @@ __global__ void prep_gv_bf16x3_kernel(const double* __restrict__ X, int64_t n, i
   out[(rest * 2 + 1) * 64 + lane] = lo;
 }
 
-struct GradArgs16 {
-  const bf16x8* xr;  // b-stream distance fragments
-  const bf16x8* xc;  // a-row distance fragments
-  const bf16x8* wf;  // b-stream fragments of W (rows role)
-  const bf16x8* uf;  // a-row fragments of w (.) U (columns role)
-  const bf16x8* gv;  // b-stream fragments of [x~ | 1 | x~^2], hi and lo
-  const double* X;
-  const double* mu;
-  Scale inv_ell;
-  int d;
-  int64_t n;
-  int64_t mpad;
-  int64_t nchunks;
-  int64_t cps;
-  double* part;
-};
-
-template <int KS, int KSC, int NG, int KIND>
-__global__ __launch_bounds__(256, 2) void grad_sweep_bf16x3_kernel(GradArgs16 a) {
-  __shared__ double sh_rows[4][16][NG * 16 + 1];
-  __shared__ double sh_red[4][GP_MAX_D + 1];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int g = lane >> 4;
-  const int64_t ablk = (int64_t)blockIdx.x * 4 + wave;
-  const bool live = ablk * 16 < a.mpad;
-
-  bf16x8 A[KS], UA[KSC];
-  if (live) {
-#pragma unroll
-    for (int q = 0; q < KS; ++q) A[q] = a.xc[(ablk * KS + q) * 64 + lane];
-#pragma unroll
-    for (int q = 0; q < KSC; ++q) UA[q] = a.uf[(ablk * KSC + q) * 64 + lane];
-  }
-  double acc64[NG][4];
-#pragma unroll
-  for (int nb = 0; nb < NG; ++nb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc64[nb][i] = 0.0;
-  double sfsum = 0.0;
-  const int64_t arow = ablk * 16 + (lane & 15);
-
-  const int64_t c_begin = (int64_t)blockIdx.y * a.cps;
-  const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
-  if (live) {
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += kGradFlush) {
-      const int64_t c1 = c0 + kGradFlush < c_end ? c0 + kGradFlush : c_end;
-      f32x4 acc[NG];
-#pragma unroll
-      for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      float sfacc = 0.f;
-      for (int64_t ch = c0; ch < c1; ++ch) {
-        f32x4 s[2], cm[2];
-#pragma unroll
-        for (int tl = 0; tl < 2; ++tl) {
-          const int64_t bblk = 2 * ch + tl;
-          s[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-          cm[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int q = 0; q < KS; ++q)
-            s[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.xr[(bblk * KS + q) * 64 + lane], A[q], s[tl], 0, 0, 0);
-#pragma unroll
-          for (int q = 0; q < KSC; ++q)
-            cm[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.wf[(bblk * KSC + q) * 64 + lane], UA[q], cm[tl], 0, 0, 0);
-        }
-        f32x8 mv;
-#pragma unroll
-        for (int tl = 0; tl < 2; ++tl)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float m, psi;
-            if constexpr (KIND == GP_MATERN52) {
-              const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(s[tl][i]));
-              const float e = __builtin_amdgcn_exp2f(-u);
-              m = __builtin_fmaf(__builtin_fmaf(u, kC2, kC1), u, 1.0f) * e;
-              psi = __builtin_fmaf(u, kC1, 1.0f) * e;
-            } else {
-              m = __builtin_amdgcn_exp2f(-__builtin_fabsf(s[tl][i]));
-              psi = m;
-            }
-            if (arow == ch * 32 + 16 * tl + 4 * g + i) {
-              m = 0.f;
-              psi = 0.f;
-            }
-            sfacc = __builtin_fmaf(m, cm[tl][i], sfacc);
-            mv[4 * tl + i] = psi * cm[tl][i];
-          }
-        const bf16x8 H = __builtin_convertvector(mv, bf16x8);
-        const f32x8 hf = __builtin_convertvector(H, f32x8);
-        const bf16x8 L = __builtin_convertvector(mv - hf, bf16x8);
-        const int64_t vbase = (ch * NG) * 2 * 64 + lane;
-#pragma unroll
-        for (int nb = 0; nb < NG; ++nb) {
-          const bf16x8 Gh = a.gv[vbase + (nb * 2 + 0) * 64];
-          const bf16x8 Gl = a.gv[vbase + (nb * 2 + 1) * 64];
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gh, acc[nb], 0, 0, 0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gl, acc[nb], 0, 0, 0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, Gh, acc[nb], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int nb = 0; nb < NG; ++nb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc64[nb][i] += (double)acc[nb][i];
-      sfsum += (double)sfacc;
-    }
-  }
-#pragma unroll
-  for (int nb = 0; nb < NG; ++nb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) sh_rows[wave][4 * g + i][16 * nb + (lane & 15)] = acc64[nb][i];
-  __syncthreads();
-  const int d = a.d;
-  double gj = 0.0;
-  if (live && lane < d) {
-    const int j = lane;
-    for (int r = 0; r < 16; ++r) {
-      const int64_t ar = ablk * 16 + r;
-      if (ar >= a.n) break;
-      const double x = (a.X[ar * d + j] - a.mu[j]) * a.inv_ell.s[j];
-      gj += x * x * sh_rows[wave][r][d] + sh_rows[wave][r][d + 1 + j] - 2.0 * x * sh_rows[wave][r][j];
-    }
-  }
-  double sfw = sfsum;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) sfw += __shfl_down(sfw, off, 64);
-  if (lane < d) sh_red[wave][lane] = gj;
-  if (lane == 0) sh_red[wave][GP_MAX_D] = live ? sfw : 0.0;
-  __syncthreads();
-  const int64_t slot = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (d + 1);
-  if (threadIdx.x < d) {
-    double sum = 0.0;
-    for (int w = 0; w < 4; ++w) sum += sh_red[w][threadIdx.x];
-    a.part[slot + threadIdx.x] = sum;
-  } else if (threadIdx.x == 64) {
-    double sum = 0.0;
-    for (int w = 0; w < 4; ++w) sum += sh_red[w][GP_MAX_D];
-    a.part[slot + d] = sum;
-  }
+// First level of the unit reduction: block b sums units [b kRedUnits, ...) per entry.
+constexpr int kRedUnits = 512;
+__global__ void grad_reduce_units_kernel(const double* __restrict__ part, int64_t nunits, int dd,
+                                         double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= dd) return;
+  const int64_t u0 = (int64_t)blockIdx.x * kRedUnits;
+  const int64_t u1 = u0 + kRedUnits < nunits ? u0 + kRedUnits : nunits;
+  double s = 0.0;
+  for (int64_t u = u0; u < u1; ++u) s += part[u * dd + j];
+  out[(int64_t)blockIdx.x * dd + j] = s;
 }
 
-// Column blocks of [x~ | 1 | x~^2], sized for the instantiated K groups so that
-// the fragment buffer and the kernel's template agree for every d.
+// Work units of the triangle sweep: for each kTriRows-row group R, the chunks
+// [4R.., nchunks) cut at multiples of cps, ordered by chunk segment then row
+// group so that concurrently running workgroups stream the same chunks.
+static int64_t tri_units(int64_t n, int64_t nchunks, int64_t cps, std::vector<int2>* out) {
+  const int64_t groups = (n + kTriRows - 1) / kTriRows;
+  const int64_t segs = (nchunks + cps - 1) / cps;
+  int64_t count = 0;
+  for (int64_t k = 0; k < segs; ++k) {
+    const int64_t seg_end = std::min((k + 1) * cps, nchunks);
+    for (int64_t R = 0; R < groups; ++R) {
+      const int64_t f = R * (kTriRows / 32);
+      if (f >= seg_end) break;
+      if (out) out->push_back(int2{(int)R, (int)std::max(f, k * cps)});
+      ++count;
+    }
+  }
+  return count;
+}
+
+static int64_t tri_cps(int64_t n, int64_t nchunks) {
+  const int64_t groups = (n + kTriRows - 1) / kTriRows;
+  const int64_t f_last = (groups - 1) * (kTriRows / 32);
+  const int64_t work = groups * nchunks - (f_last + kTriRows / 32) * groups / 2;  // chunk visits, approximately
+  return std::min<int64_t>(1024, std::max<int64_t>(32, work / 4096));
+}
+
+// Column blocks of [x~ | 1 | x~^2] of the FP32 form, sized for the instantiated
+// K groups so that the fragment buffer and the kernel's template agree for every d.
 static int ncb_fp32(int kq) { return 2 * kq + 1; }  // d <= 16 kq
-static int ncb_bf16x3(int ks) {                      // d <= (32 ks - 6) / 3, at most 64
-  const int dmax = std::min(64, (32 * ks - 6) / 3);
-  return (2 * dmax + 1 + 15) / 16;
-}
 
 struct GradGeom {
   bool mixed;
-  int ks, ksc, ncb;  // distance K steps, C K steps, [x~|1|x~^2] blocks
-  int64_t npad, mpad, nchunks, cps, nsplit, nblk_x;
+  int ks, ksc, ncb;  // distance K steps, C K steps, form column blocks
+  int nj;            // BF16X3: 16-column blocks of x~
+  int64_t npad, mpad, nchunks;
+  int64_t cps;       // chunks per split (FP32) / unit alignment (BF16X3)
+  int64_t nsplit, nblk_x;  // FP32 form: full-matrix splits x row blocks
+  int64_t nunits;          // BF16X3 form: triangle work units
+  int64_t nparts() const { return mixed ? nunits : nsplit * nblk_x; }
 };
 
 static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
-  GradGeom g;
+  GradGeom g{};
   g.mixed = precision == GP_PREC_BF16X3;
   g.ks = kmm_ksteps(precision, d);
+  g.npad = (n + 31) / 32 * 32;
+  g.nchunks = g.npad / 32;
   if (g.mixed) {
-    g.ksc = (3 * t + 31) / 32;
-    g.ncb = ncb_bf16x3(g.ks);
+    g.ksc = grad_tri_ksc(t);
+    g.nj = (d + 15) / 16;
+    g.ncb = 2 * g.nj;
+    g.mpad = (n + kTriRows - 1) / kTriRows * kTriRows;
+    g.cps = tri_cps(n, g.nchunks);
+    g.nunits = tri_units(n, g.nchunks, g.cps, nullptr);
   } else {
     g.ksc = (t + 15) / 16;
     g.ncb = ncb_fp32(g.ks);
+    g.mpad = (n + 255) / 256 * 256;
+    g.nblk_x = g.mpad / 64;
+    const int64_t want = std::max<int64_t>(1, (2048 + g.nblk_x - 1) / g.nblk_x);
+    g.cps = std::max<int64_t>(2, (g.nchunks + want - 1) / want);
+    g.nsplit = (g.nchunks + g.cps - 1) / g.cps;
   }
-  g.npad = (n + 31) / 32 * 32;
-  g.mpad = (n + 255) / 256 * 256;
-  g.nchunks = g.npad / 32;
-  g.nblk_x = g.mpad / 64;
-  const int64_t want = std::max<int64_t>(1, (2048 + g.nblk_x - 1) / g.nblk_x);
-  g.cps = std::max<int64_t>(2, (g.nchunks + want - 1) / want);
-  g.nsplit = (g.nchunks + g.cps - 1) / g.cps;
   return g;
 }
 
 size_t grad_ws_bytes(int precision, int d, int64_t n, int t) {
   const GradGeom g = grad_geom(precision, d, n, t);
-  if (g.ks < 0) return 0;
+  if (g.ks < 0 || g.ksc < 0) return 0;
+  const int64_t nparts = g.nparts();
   size_t b = kmm_plan_bytes(precision, d, n, n, true, 1);
-  b += align256((size_t)std::max(g.npad, g.mpad) * g.ksc * 64);  // W fragments
-  b += align256((size_t)g.mpad * g.ksc * 64);                    // w U fragments
-  b += align256((size_t)g.npad * g.ncb * 64);                    // [x~|1|x~^2] fragments (hi+lo or float4 pairs)
-  b += align256((size_t)g.nsplit * g.nblk_x * (d + 1) * 8);      // partials
+  b += align256((size_t)std::max(g.npad, g.mpad) * g.ksc * 64);  // b-side C fragments
+  b += align256((size_t)g.mpad * g.ksc * 64);                    // a-side C fragments
+  b += align256((size_t)g.npad * g.ncb * 64);                    // form fragments (hi+lo or float4 pairs)
+  b += align256((size_t)nparts * (d + 1) * 8);                   // partials
+  b += align256((size_t)((nparts + kRedUnits - 1) / kRedUnits) * (d + 1) * 8);  // first-level sums
   b += align256((size_t)(d + 1) * 8);                            // reduced
-  b += align256((size_t)t * 8) + align256((size_t)d * 8);        // weights, mean
+  b += align256((size_t)t * 8) + 2 * align256((size_t)d * 8);    // weights, mean, 1/l
+  b += align256((size_t)std::max<int64_t>(g.nunits, 1) * sizeof(int2));  // unit table
   b += align256((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t) * 8);  // reductions
   b += align256((size_t)t * 8);                                  // U_c . W_c
   return b + 4096;
@@ -570,30 +468,6 @@ static bool launch_grad1(int kqc, int ng, int kind, dim3 grid, const GradArgs& a
   }
 }
 
-template <int KS, int KSC>
-static bool launch_g16_b(int ng, int kind, dim3 grid, const GradArgs16& a, hipStream_t st) {
-  constexpr int NG = (2 * ((32 * KS - 6) / 3 < 64 ? (32 * KS - 6) / 3 : 64) + 1 + 15) / 16;
-  if (ng != NG) return false;
-  if (kind == GP_MATERN52)
-    grad_sweep_bf16x3_kernel<KS, KSC, NG, GP_MATERN52><<<grid, 256, 0, st>>>(a);
-  else
-    grad_sweep_bf16x3_kernel<KS, KSC, NG, GP_RBF><<<grid, 256, 0, st>>>(a);
-  return true;
-}
-
-template <int KS>
-static bool launch_g16_a(int ksc, int ng, int kind, dim3 grid, const GradArgs16& a, hipStream_t st) {
-  switch (ksc) {
-    case 1: return launch_g16_b<KS, 1>(ng, kind, grid, a, st);
-    case 2: return launch_g16_b<KS, 2>(ng, kind, grid, a, st);
-    case 3: return launch_g16_b<KS, 3>(ng, kind, grid, a, st);
-    case 4: return launch_g16_b<KS, 4>(ng, kind, grid, a, st);
-    case 5: return launch_g16_b<KS, 5>(ng, kind, grid, a, st);
-    case 6: return launch_g16_b<KS, 6>(ng, kind, grid, a, st);
-    default: return false;
-  }
-}
-
 int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t n, const double* U, int64_t ldu,
                  const double* W, int64_t ldw, int t, const double* colw, double* grad, void* ws, size_t ws_bytes,
                  hipStream_t st) {
@@ -601,67 +475,75 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   const GradGeom g = grad_geom(precision, d, n, t);
   const size_t kb = kmm_plan_bytes(precision, d, n, n, true, 1);
   KmmPlan plan;
-  if (g.ks < 0 || !kmm_plan_init(plan, kern, precision, n, n, true, 1, ws, kb))
+  if (g.ks < 0 || g.ksc < 0 || !kmm_plan_init(plan, kern, precision, n, n, true, 1, ws, kb))
     return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace too small");
+  const int64_t nparts = g.nparts();
+  const int64_t nred = (nparts + kRedUnits - 1) / kRedUnits;
   Carve cv((char*)ws + align256(kb), ws_bytes - align256(kb));
   char* wf = cv.take<char>((size_t)std::max(g.npad, g.mpad) * g.ksc * 64);
   char* uf = cv.take<char>((size_t)g.mpad * g.ksc * 64);
   char* gv = cv.take<char>((size_t)g.npad * g.ncb * 64);
-  double* part = cv.take<double>((size_t)g.nsplit * g.nblk_x * (d + 1));
+  double* part = cv.take<double>((size_t)nparts * (d + 1));
+  double* part2 = cv.take<double>((size_t)nred * (d + 1));
   double* red = cv.take<double>(d + 1);
   double* wdev = cv.take<double>(t);
   double* mu = cv.take<double>(d);
+  double* inv_dev = cv.take<double>(d);
+  int2* unit_dev = cv.take<int2>((size_t)std::max<int64_t>(g.nunits, 1));
   double* rpart = cv.take<double>((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t));
   double* uw = cv.take<double>(t);
   if (!uw) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace layout failed");
+  std::vector<double> invh(d);
+  for (int j = 0; j < d; ++j) invh[j] = 1.0 / kern->lengthscale[j];
+  std::vector<int2> units;
   GPK_HIP(hipMemcpyAsync(wdev, colw, sizeof(double) * t, hipMemcpyHostToDevice, st));
+  GPK_HIP(hipMemcpyAsync(inv_dev, invh.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
   {
     const RowSplit rs = row_split(n, kDotBlocks);
     colmean_partial_kernel<<<(unsigned)rs.nblk, 128, 0, st>>>(X, n, d, rs.rows_per_blk, rpart);
     colmean_final_kernel<<<1, 128, 0, st>>>(rpart, rs.nblk, d, n, mu);
   }
   GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
-  Scale inv{};
-  for (int j = 0; j < d; ++j) inv.s[j] = 1.0 / kern->lengthscale[j];
-  const int64_t nbr = std::max(g.npad, g.mpad) / 16;
-  const int64_t nba = g.mpad / 16;
   const unsigned thr = 256;
-  dim3 grid((unsigned)g.nblk_x, (unsigned)g.nsplit);
   bool ok = false;
   if (g.mixed) {
+    units.reserve((size_t)g.nunits);
+    tri_units(n, g.nchunks, g.cps, &units);
+    GPK_HIP(hipMemcpyAsync(unit_dev, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice, st));
+    const int64_t nbr = g.npad / 16, nba = g.mpad / 16;
     const int64_t tot = nbr * g.ksc * 64;
-    prep_matfrag_bf16x3_kernel<<<(unsigned)((tot + thr - 1) / thr), thr, 0, st>>>(W, ldw, n, t, nullptr, nbr, g.ksc,
-                                                                                 0, (bf16x8*)wf);
+    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot + thr - 1) / thr), thr, 0, st>>>(W, U, n, n, t, nullptr, nbr,
+                                                                                  g.ksc, 0, (bf16x8*)wf);
     const int64_t tot2 = nba * g.ksc * 64;
-    prep_matfrag_bf16x3_kernel<<<(unsigned)((tot2 + thr - 1) / thr), thr, 0, st>>>(U, ldu, n, t, wdev, nba, g.ksc,
-                                                                                  1, (bf16x8*)uf);
+    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot2 + thr - 1) / thr), thr, 0, st>>>(U, W, n, n, t, wdev, nba,
+                                                                                   g.ksc, 1, (bf16x8*)uf);
     const int64_t tot3 = g.nchunks * g.ncb * 64;
-    prep_gv_bf16x3_kernel<<<(unsigned)((tot3 + thr - 1) / thr), thr, 0, st>>>(X, n, d, inv, mu, g.nchunks, g.ncb,
-                                                                              (bf16x8*)gv);
+    prep_formfrag_bf16x3_kernel<<<(unsigned)((tot3 + thr - 1) / thr), thr, 0, st>>>(X, n, d, g.nj, inv_dev, mu,
+                                                                                   g.nchunks, (bf16x8*)gv);
     GPK_HIP(hipGetLastError());
-    GradArgs16 a;
+    GradTriArgs a;
     a.xr = (const bf16x8*)plan.xr;
     a.xc = (const bf16x8*)plan.xc;
-    a.wf = (const bf16x8*)wf;
-    a.uf = (const bf16x8*)uf;
+    a.cb = (const bf16x8*)wf;
+    a.ca = (const bf16x8*)uf;
     a.gv = (const bf16x8*)gv;
+    a.units = unit_dev;
     a.X = X;
     a.mu = mu;
-    a.inv_ell = inv;
+    a.inv_ell = inv_dev;
     a.d = d;
     a.n = n;
-    a.mpad = g.mpad;
     a.nchunks = g.nchunks;
-    a.cps = g.cps;
+    a.cps = (int)g.cps;
     a.part = part;
-    switch (g.ks) {
-      case 2: ok = launch_g16_a<2>(g.ksc, g.ncb, kern->kind, grid, a, st); break;
-      case 4: ok = launch_g16_a<4>(g.ksc, g.ncb, kern->kind, grid, a, st); break;
-      case 5: ok = launch_g16_a<5>(g.ksc, g.ncb, kern->kind, grid, a, st); break;
-      case 7: ok = launch_g16_a<7>(g.ksc, g.ncb, kern->kind, grid, a, st); break;
-      default: ok = false;
-    }
+    ok = kern->kind == GP_MATERN52 ? launch_grad_tri_matern(g.ks, g.nj, g.ksc, (unsigned)g.nunits, a, st)
+                                   : launch_grad_tri_rbf(g.ks, g.nj, g.ksc, (unsigned)g.nunits, a, st);
   } else {
+    Scale inv{};
+    for (int j = 0; j < d; ++j) inv.s[j] = invh[j];
+    const int64_t nbr = std::max(g.npad, g.mpad) / 16;
+    const int64_t nba = g.mpad / 16;
+    dim3 grid((unsigned)g.nblk_x, (unsigned)g.nsplit);
     const int64_t tot = nbr * g.ksc * 64;
     prep_colfrag_kernel<<<(unsigned)((tot + thr - 1) / thr), thr, 0, st>>>(W, ldw, n, t, nullptr, nbr, g.ksc,
                                                                           (f32x4*)wf);
@@ -699,7 +581,8 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   }
   if (!ok) return fail(GP_EINVAL, "gp_kmm_grad: unsupported d=%d or t=%d (d <= 64, t <= 64)", d, t);
   GPK_HIP(hipGetLastError());
-  grad_final_kernel<<<1, 256, 0, st>>>(part, g.nsplit * g.nblk_x, d + 1, red);
+  grad_reduce_units_kernel<<<(unsigned)nred, 128, 0, st>>>(part, nparts, d + 1, part2);
+  grad_final_kernel<<<1, 256, 0, st>>>(part2, nred, d + 1, red);
   GPK_HIP(coldot(U, W, n, t, uw, rpart, st));  // requires ldu == ldw == n
   std::vector<double> r(d + 1), uwh(t);
   GPK_HIP(hipMemcpyAsync(r.data(), red, sizeof(double) * (d + 1), hipMemcpyDeviceToHost, st));

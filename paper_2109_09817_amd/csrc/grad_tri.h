@@ -1,0 +1,61 @@
+// Upper-triangle tile sweep of the hyperparameter bilinear forms (BF16X3).
+//
+// The mBCG gradient estimate (Sec. 3.2, the derivative of Eq. 2) needs, for
+// every lengthscale j,
+//   g_j = sum_{a != b} psi(r_ab) C_ab (x~_aj - x~_bj)^2,   C_ab = sum_c w_c U_ac W_bc,
+// and g_{s_f} = sum_{a != b} k(r_ab) C_ab.  psi, k and the squared difference are
+// symmetric in (a, b), so both sums run over the pairs a < b only, with C
+// replaced by its symmetric part C^s_ab = C_ab + C_ba
+//   = sum_c w_c (U_ac W_bc + W_ac U_bc).
+// Each unordered pair is evaluated once: half the distance products, half the
+// kernel evaluations of the full-matrix sweep.
+//
+// Work unit: a row group of 128 rows a (8 waves x one 16-row block, held in
+// registers) against a range of 32-point chunks b at or after the group's own
+// first chunk; pairs with b <= a inside a chunk that straddles a block are
+// masked.  Per (16 rows) x (32 points) tile, on the BF16 matrix cores:
+//   S    = |x~_a - x~_b|^2          (distance, K = 3d + 6 split terms)
+//   C^s  = [W_b | U_b] . [w U_a | w W_a]^T   (K = 2t, split three ways)
+//   P    = psi(S) C^s, its row sums, and sum k(S) C^s   (registers, FP32)
+//   Q, T = P . [x~_b | x~_b^2]       (2 ceil(d/16) blocks of 16 columns)
+// Every 32 chunks the FP32 sums are folded into per-lane FP64 partials of
+//   g_j += sum_a x~_aj^2 R_a - 2 x~_aj Q_aj + T_aj,  R_a = sum_b P_ab.
+// The b-side fragments of each chunk are staged in LDS, double-buffered, and
+// shared by the 8 waves.
+#pragma once
+
+#include "internal.h"
+
+namespace gpk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct GradTriArgs {
+  const bf16x8* xr;     // b-stream distance fragments (A operand)
+  const bf16x8* xc;     // a-row distance fragments (B operand)
+  const bf16x8* cb;     // b-stream fragments of [W | U]        (A operand, K = 6t: hi | hi | lo)
+  const bf16x8* ca;     // a-row fragments of [w U | w W]       (B operand, K = 6t: hi | lo | hi)
+  const bf16x8* gv;     // b-stream fragments of [x~ | x~^2]    (B operand of the forms, hi and lo)
+  const int2* units;    // per workgroup: (row group, first chunk)
+  const double* X;      // n x d row-major
+  const double* mu;     // column means (d)
+  const double* inv_ell;  // 1 / lengthscale (d)
+  int d;
+  int64_t n;
+  int64_t nchunks;
+  int cps;              // chunk-range alignment of the units
+  double* part;         // per unit: g_1..g_d, g_{s_f} (unscaled)
+};
+
+constexpr int kTriWaves = 8;
+constexpr int kTriRows = 16 * kTriWaves;  // rows per row group
+constexpr int kTriFlush = 32;             // chunks per FP32 accumulation window
+
+// Launch one instantiation; false if (ks, nj, ksc) has none.
+bool launch_grad_tri_matern(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st);
+bool launch_grad_tri_rbf(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st);
+
+// Instantiated chunk widths of the C^s product (K steps of 32 for 6t terms).
+int grad_tri_ksc(int t);
+
+}  // namespace gpk

@@ -1,0 +1,228 @@
+// Kernel template of the upper-triangle hyperparameter-form sweep (see grad_tri.h)
+// and its instantiation table; included by one translation unit per kernel kind.
+#pragma once
+
+#include "grad_tri.h"
+#include "mfma_bf16.h"
+
+namespace gpk {
+
+// LDS image of one 32-point chunk, in 64-lane units of 16 bytes:
+// [2 KS distance fragments | 2 KSC C fragments | 2 NJ (hi, lo) pairs of form fragments].
+template <int KS, int KSC, int NJ>
+struct TriChunk {
+  static constexpr int kDist = 2 * KS * 64;
+  static constexpr int kC = 2 * KSC * 64;
+  static constexpr int kG = 2 * (2 * NJ) * 64;
+  static constexpr int kAll = kDist + kC + kG;
+  static constexpr int kPerThread = (kAll + 64 * kTriWaves - 1) / (64 * kTriWaves);
+};
+
+template <int KS, int KSC, int NJ, int KIND>
+__global__ __launch_bounds__(64 * kTriWaves, 1) void grad_tri_bf16x3_kernel(GradTriArgs a) {
+  constexpr int NG = 2 * NJ;
+  using TC = TriChunk<KS, KSC, NJ>;
+  __shared__ bf16x8 stage[2][TC::kAll];
+  __shared__ double red[kTriWaves][GP_MAX_D + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;
+  const int c16 = lane & 15;
+  const int2 unit = a.units[blockIdx.x];
+  const int64_t ar = (int64_t)unit.x * kTriRows + 16 * wave;  // first row of this wave's block
+  const int64_t ablk = ar / 16;
+  const int64_t c_begin = unit.y;
+  const int64_t c_lim = (c_begin / a.cps + 1) * a.cps;
+  const int64_t c_end = c_lim < a.nchunks ? c_lim : a.nchunks;
+
+  bf16x8 A[KS], CA[KSC];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) A[ks] = a.xc[(ablk * KS + ks) * 64 + lane];
+#pragma unroll
+  for (int q = 0; q < KSC; ++q) CA[q] = a.ca[(ablk * KSC + q) * 64 + lane];
+
+  f32x4 acc[NG];
+#pragma unroll
+  for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float racc = 0.f, sfacc = 0.f;
+  double g64[NJ];
+#pragma unroll
+  for (int cb = 0; cb < NJ; ++cb) g64[cb] = 0.0;
+  double sf64 = 0.0;
+
+  bf16x8 pre[TC::kPerThread];
+  auto fetch = [&](int64_t ch) {
+#pragma unroll
+    for (int r = 0; r < TC::kPerThread; ++r) {
+      const int u = tid + 64 * kTriWaves * r;
+      if (u < TC::kDist) {
+        pre[r] = a.xr[(2 * ch * KS) * 64 + u];
+      } else if (u < TC::kDist + TC::kC) {
+        pre[r] = a.cb[(2 * ch * KSC) * 64 + (u - TC::kDist)];
+      } else if (u < TC::kAll) {
+        pre[r] = a.gv[(ch * NG * 2) * 64 + (u - TC::kDist - TC::kC)];
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < TC::kPerThread; ++r) {
+      const int u = tid + 64 * kTriWaves * r;
+      if (u < TC::kAll) stage[buf][u] = pre[r];
+    }
+  };
+  // Fold the FP32 window into the FP64 partials of g_j (j = 16 cb + c16).
+  auto flush = [&]() {
+    float rf = racc;  // row sums of P: lane holds row ar + c16 over 8 of the points
+    rf += __shfl_xor(rf, 16, 64);
+    rf += __shfl_xor(rf, 32, 64);
+    double Ri[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Ri[i] = (double)__shfl(rf, 4 * g + i, 64);
+#pragma unroll
+    for (int cb = 0; cb < NJ; ++cb) {
+      const int j = 16 * cb + c16;
+      if (j < a.d) {
+        const double m = a.mu[j], s = a.inv_ell[j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t row = ar + 4 * g + i;
+          if (row < a.n) {
+            const double x = (a.X[row * a.d + j] - m) * s;
+            g64[cb] += x * x * Ri[i] - 2.0 * x * (double)acc[cb][i] + (double)acc[NJ + cb][i];
+          }
+        }
+      }
+    }
+    sf64 += (double)sfacc;
+#pragma unroll
+    for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    racc = 0.f;
+    sfacc = 0.f;
+  };
+
+  fetch(c_begin);
+  stash(0);
+  __syncthreads();
+  int window = 0;
+  for (int64_t ch = c_begin; ch < c_end; ++ch) {
+    const int cur = (int)((ch - c_begin) & 1);
+    const bool more = ch + 1 < c_end;
+    if (more) fetch(ch + 1);
+    const int64_t b0 = ch * 32;
+    if (b0 + 31 > ar) {  // the tile holds some pair b > a
+      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+      f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][ks * 64 + lane], A[ks], s0, 0, 0, 0);
+        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][(KS + ks) * 64 + lane], A[ks], s1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < KSC; ++q) {
+        q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[q], q0, 0, 0, 0);
+        q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + (KSC + q) * 64 + lane], CA[q], q1, 0,
+                                                     0, 0);
+      }
+      if (b0 < ar + 16) {  // straddles the block: keep b > a only
+        const int64_t am = ar + c16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (b0 + 4 * g + i <= am) q0[i] = 0.f;
+          if (b0 + 16 + 4 * g + i <= am) q1[i] = 0.f;
+        }
+      }
+      f32x8 pv;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float S = __builtin_fabsf(k < 4 ? s0[k] : s1[k - 4]);
+        const float cs = k < 4 ? q0[k] : q1[k - 4];
+        float m, psi;
+        if constexpr (KIND == GP_MATERN52) {
+          const float u = __builtin_amdgcn_sqrtf(S);
+          const float e = __builtin_amdgcn_exp2f(-u);
+          psi = __builtin_fmaf(u, kMaternC1, 1.0f) * e;       // (1 + sqrt5 r) e^{-sqrt5 r}
+          m = __builtin_fmaf(kMaternC2 * S, e, psi);          // (1 + sqrt5 r + 5r^2/3) e^{-sqrt5 r}
+        } else {
+          m = __builtin_amdgcn_exp2f(-S);
+          psi = m;
+        }
+        const float p = psi * cs;
+        pv[k] = p;
+        racc += p;
+        sfacc = __builtin_fmaf(m, cs, sfacc);
+      }
+      bf16x8 H, L;
+      split_bf16x8(pv, H, L);
+#pragma unroll
+      for (int nb = 0; nb < NG; ++nb) {
+        const bf16x8 Gh = stage[cur][TC::kDist + TC::kC + (2 * nb) * 64 + lane];
+        const bf16x8 Gl = stage[cur][TC::kDist + TC::kC + (2 * nb + 1) * 64 + lane];
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gh, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gl, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, Gh, acc[nb], 0, 0, 0);
+      }
+    }
+    if (++window == kTriFlush || !more) {
+      flush();
+      window = 0;
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+  }
+
+  // unit partial: sum over the 16 rows of every wave, then over the waves
+#pragma unroll
+  for (int cb = 0; cb < NJ; ++cb) {
+    double v = g64[cb];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (g == 0 && 16 * cb + c16 < a.d) red[wave][16 * cb + c16] = v;
+  }
+  double s = sf64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) red[wave][a.d] = s;
+  __syncthreads();
+  if (tid <= a.d) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kTriWaves; ++w) t += red[w][tid];
+    a.part[(int64_t)blockIdx.x * (a.d + 1) + tid] = t;
+  }
+}
+
+template <int KS, int NJ, int KSC, int KIND>
+static void tri_launch(unsigned units, const GradTriArgs& a, hipStream_t st) {
+  grad_tri_bf16x3_kernel<KS, KSC, NJ, KIND><<<units, 64 * kTriWaves, 0, st>>>(a);
+}
+
+template <int KS, int NJ, int KIND>
+static bool tri_ksc(int ksc, unsigned units, const GradTriArgs& a, hipStream_t st) {
+  switch (ksc) {
+    case 1: tri_launch<KS, NJ, 1, KIND>(units, a, st); return true;
+    case 2: tri_launch<KS, NJ, 2, KIND>(units, a, st); return true;
+    case 3: tri_launch<KS, NJ, 3, KIND>(units, a, st); return true;
+    case 4: tri_launch<KS, NJ, 4, KIND>(units, a, st); return true;
+    case 6: tri_launch<KS, NJ, 6, KIND>(units, a, st); return true;
+    case 8: tri_launch<KS, NJ, 8, KIND>(units, a, st); return true;
+    case 12: tri_launch<KS, NJ, 12, KIND>(units, a, st); return true;
+    default: return false;
+  }
+}
+
+// (KS, NJ) pairs that occur for d <= 64: KS = 2 (d <= 19), 4 (d <= 40), 5 (d <= 51), 7 (d <= 64).
+template <int KIND>
+static bool tri_dispatch(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st) {
+  if (ks == 2 && nj == 1) return tri_ksc<2, 1, KIND>(ksc, units, a, st);
+  if (ks == 2 && nj == 2) return tri_ksc<2, 2, KIND>(ksc, units, a, st);
+  if (ks == 4 && nj == 2) return tri_ksc<4, 2, KIND>(ksc, units, a, st);
+  if (ks == 4 && nj == 3) return tri_ksc<4, 3, KIND>(ksc, units, a, st);
+  if (ks == 5 && nj == 3) return tri_ksc<5, 3, KIND>(ksc, units, a, st);
+  if (ks == 5 && nj == 4) return tri_ksc<5, 4, KIND>(ksc, units, a, st);
+  if (ks == 7 && nj == 4) return tri_ksc<7, 4, KIND>(ksc, units, a, st);
+  return false;
+}
+
+}  // namespace gpk

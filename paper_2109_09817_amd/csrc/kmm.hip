@@ -30,6 +30,7 @@
 //   FP32:   v_mfma_f32_16x16x4_f32 for both products; the squared norms
 //           initialise the distance accumulator.
 #include "internal.h"
+#include "mfma_bf16.h"
 
 #include <algorithm>
 #include <mutex>
@@ -37,17 +38,6 @@
 #include <cmath>
 
 namespace gpk {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
-
-// log2(e) * sqrt(5) scales x/l so that S = u^2 with u = sqrt5 r log2(e):
-// exp(-sqrt5 r) = exp2(-u) and 1 + sqrt5 r + 5r^2/3 = 1 + u ln2 + (u ln2)^2 / 3.
-// (The scales are evaluated on the host from M_LOG2E; see make_scale.)
-constexpr float kMaternC1 = (float)M_LN2;                  // ln 2
-constexpr float kMaternC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
-// RBF: S = r^2 log2(e) / 2 so that exp(-r^2/2) = exp2(-S).
 
 constexpr int kFlush = 32;  // 32-point chunks accumulated in FP32 before the FP64 flush
 
@@ -188,11 +178,6 @@ __global__ void prep_frag_fp32_kernel(const double* __restrict__ X, const double
   }
 }
 
-// K index permutation of the M . V product: slot (g, j) of a lane holds point
-// b = 4g + j (j < 4) or 16 + 4g + j - 4 (j >= 4) of the 32-point chunk, which is
-// where the two distance tiles' accumulators leave them.
-__device__ __forceinline__ int vperm(int g, int j) { return j < 4 ? 4 * g + j : 12 + 4 * g + j; }
-
 // BF16X3 V fragments: (chunk, cb, hl, lane) -> 8 BF16 of V[b = 32 chunk + vperm(g, j)]
 // [c = 16 cb + lane%16], hl = 0 hi, 1 lo.
 __global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ col0,
@@ -263,27 +248,6 @@ template <int NT>
 struct NAOf {
   static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
 };
-
-// Split 8 FP32 values into BF16 hi = RNE(m) and lo = RNE(m - hi), two values per
-// v_cvt_pk_bf16_f32; hi is widened back with one shift or mask per value.
-__device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& L) {
-  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-  typedef float f32x2 __attribute__((ext_vector_type(2)));
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const f32x2 v = {m[2 * p], m[2 * p + 1]};
-    const bf16x2 h = __builtin_convertvector(v, bf16x2);
-    const uint32_t hb = __builtin_bit_cast(uint32_t, h);
-    const float h0 = __builtin_bit_cast(float, hb << 16);
-    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
-    const f32x2 r = {v[0] - h0, v[1] - h1};
-    const bf16x2 l = __builtin_convertvector(r, bf16x2);
-    H[2 * p] = h[0];
-    H[2 * p + 1] = h[1];
-    L[2 * p] = l[0];
-    L[2 * p + 1] = l[1];
-  }
-}
 
 // One 32-point chunk of the b stream staged in LDS: the 2 KS point fragments
 // followed by the NT (hi, lo) V fragments, 64 lanes x 16 bytes each.

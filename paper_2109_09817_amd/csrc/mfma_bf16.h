@@ -1,0 +1,49 @@
+// Register types and helpers shared by the BF16X3 tile sweeps (K_hat V, the
+// hyperparameter forms and prediction).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace gpk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+
+// log2(e) * sqrt(5) scales x/l so that S = u^2 with u = sqrt5 r log2(e):
+// exp(-sqrt5 r) = exp2(-u) and 1 + sqrt5 r + 5r^2/3 = 1 + u ln2 + (u ln2)^2 / 3.
+// (The scales are evaluated on the host from M_LOG2E; see make_scale.)
+constexpr float kMaternC1 = (float)M_LN2;                  // ln 2
+constexpr float kMaternC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
+// RBF: S = r^2 log2(e) / 2 so that exp(-r^2/2) = exp2(-S).
+
+// Split 8 FP32 values into BF16 hi = RNE(m) and lo = RNE(m - hi), two values per
+// v_cvt_pk_bf16_f32; hi is widened back with one shift or mask per value.
+__device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& L) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const f32x2 v = {m[2 * p], m[2 * p + 1]};
+    const bf16x2 h = __builtin_convertvector(v, bf16x2);
+    const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+    const float h0 = __builtin_bit_cast(float, hb << 16);
+    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+    const f32x2 r = {v[0] - h0, v[1] - h1};
+    const bf16x2 l = __builtin_convertvector(r, bf16x2);
+    H[2 * p] = h[0];
+    H[2 * p + 1] = h[1];
+    L[2 * p] = l[0];
+    L[2 * p + 1] = l[1];
+  }
+}
+
+// K position -> point of a 32-point chunk, for an operand built from the two
+// 16x16 distance accumulators of the chunk (lane l holds rows 4(l/16)+i of
+// each): K = 8(l/16) + j takes point vperm(l/16, j).
+__device__ __forceinline__ int vperm(int g, int j) { return j < 4 ? 4 * g + j : 12 + 4 * g + j; }
+
+}  // namespace gpk

@@ -209,7 +209,7 @@ def test_mll_and_grad_matches_oracle_pipeline(prec, cond):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
-@pytest.mark.parametrize("n,d,t", [(1500, 48, 9), (700, 7, 3), (2049, 32, 33), (1100, 64, 64)])
+@pytest.mark.parametrize("n,d,t", [(1500, 48, 9), (700, 7, 3), (2049, 32, 33), (1100, 64, 64), (5000, 48, 16)])
 def test_kmm_grad_matches_oracle(n, d, t, kind, prec):
     from paper_2109_09817_amd import gp
     X, y, th0 = _problem(n, d, True)
