@@ -357,17 +357,17 @@ __global__ void grad_reduce_units_kernel(const double* __restrict__ part, int64_
   out[(int64_t)blockIdx.x * dd + j] = s;
 }
 
-// Work units of the triangle sweep: for each kTriRows-row group R, the chunks
-// [4R.., nchunks) cut at multiples of cps, ordered by chunk segment then row
-// group so that concurrently running workgroups stream the same chunks.
-static int64_t tri_units(int64_t n, int64_t nchunks, int64_t cps, std::vector<int2>* out) {
-  const int64_t groups = (n + kTriRows - 1) / kTriRows;
+// Work units of the triangle sweep: for each row group R (`rows` rows), the
+// chunks [R rows/32, nchunks) cut at multiples of cps, ordered by chunk segment
+// then row group so that concurrently running workgroups stream the same chunks.
+static int64_t tri_units(int64_t n, int64_t rows, int64_t nchunks, int64_t cps, std::vector<int2>* out) {
+  const int64_t groups = (n + rows - 1) / rows;
   const int64_t segs = (nchunks + cps - 1) / cps;
   int64_t count = 0;
   for (int64_t k = 0; k < segs; ++k) {
     const int64_t seg_end = std::min((k + 1) * cps, nchunks);
     for (int64_t R = 0; R < groups; ++R) {
-      const int64_t f = R * (kTriRows / 32);
+      const int64_t f = R * (rows / 32);
       if (f >= seg_end) break;
       if (out) out->push_back(int2{(int)R, (int)std::max(f, k * cps)});
       ++count;
@@ -376,10 +376,10 @@ static int64_t tri_units(int64_t n, int64_t nchunks, int64_t cps, std::vector<in
   return count;
 }
 
-static int64_t tri_cps(int64_t n, int64_t nchunks) {
-  const int64_t groups = (n + kTriRows - 1) / kTriRows;
-  const int64_t f_last = (groups - 1) * (kTriRows / 32);
-  const int64_t work = groups * nchunks - (f_last + kTriRows / 32) * groups / 2;  // chunk visits, approximately
+static int64_t tri_cps(int64_t n, int64_t rows, int64_t nchunks) {
+  const int64_t groups = (n + rows - 1) / rows;
+  const int64_t f_last = (groups - 1) * (rows / 32);
+  const int64_t work = groups * nchunks - (f_last + rows / 32) * groups / 2;  // chunk visits, approximately
   return std::min<int64_t>(1024, std::max<int64_t>(32, work / 4096));
 }
 
@@ -391,6 +391,7 @@ struct GradGeom {
   bool mixed;
   int ks, ksc, ncb;  // distance K steps, C K steps, form column blocks
   int nj;            // BF16X3: 16-column blocks of x~
+  int64_t rows;      // BF16X3: rows per row group
   int64_t npad, mpad, nchunks;
   int64_t cps;       // chunks per split (FP32) / unit alignment (BF16X3)
   int64_t nsplit, nblk_x;  // FP32 form: full-matrix splits x row blocks
@@ -408,9 +409,10 @@ static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
     g.ksc = grad_tri_ksc(t);
     g.nj = (d + 15) / 16;
     g.ncb = 2 * g.nj;
-    g.mpad = (n + kTriRows - 1) / kTriRows * kTriRows;
-    g.cps = tri_cps(n, g.nchunks);
-    g.nunits = tri_units(n, g.nchunks, g.cps, nullptr);
+    g.rows = g.ksc > 0 ? tri_rows(g.ks, g.ksc, g.nj) : 16 * kTriWaves;
+    g.mpad = (n + g.rows - 1) / g.rows * g.rows;
+    g.cps = tri_cps(n, g.rows, g.nchunks);
+    g.nunits = tri_units(n, g.rows, g.nchunks, g.cps, nullptr);
   } else {
     g.ksc = (t + 15) / 16;
     g.ncb = ncb_fp32(g.ks);
@@ -508,7 +510,7 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   bool ok = false;
   if (g.mixed) {
     units.reserve((size_t)g.nunits);
-    tri_units(n, g.nchunks, g.cps, &units);
+    tri_units(n, g.rows, g.nchunks, g.cps, &units);
     GPK_HIP(hipMemcpyAsync(unit_dev, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice, st));
     const int64_t nbr = g.npad / 16, nba = g.mpad / 16;
     const int64_t tot = nbr * g.ksc * 64;

@@ -10,8 +10,8 @@
 // Each unordered pair is evaluated once: half the distance products, half the
 // kernel evaluations of the full-matrix sweep.
 //
-// Work unit: a row group of 128 rows a (8 waves x one 16-row block, held in
-// registers) against a range of 32-point chunks b at or after the group's own
+// Work unit: a row group of 128 or 256 rows a (8 waves x one or two 16-row
+// blocks, held in registers) against a range of 32-point chunks b at or after the group's own
 // first chunk; pairs with b <= a inside a chunk that straddles a block are
 // masked.  Per (16 rows) x (32 points) tile, on the BF16 matrix cores:
 //   S    = |x~_a - x~_b|^2          (distance, K = 3d + 6 split terms)
@@ -48,8 +48,14 @@ struct GradTriArgs {
 };
 
 constexpr int kTriWaves = 8;
-constexpr int kTriRows = 16 * kTriWaves;  // rows per row group
-constexpr int kTriFlush = 32;             // chunks per FP32 accumulation window
+constexpr int kTriFlush = 32;  // chunks per FP32 accumulation window
+
+// 16-row blocks per wave: two while they fit in 256 VGPRs without spilling
+// (the staged b-side fragments then serve two tiles per LDS read), else one.
+// The bound is fitted to the compiled register counts of the instantiations.
+constexpr int tri_na(int ks, int ksc, int nj) { return 16 * ks + 8 * ksc + 24 * nj <= 176 ? 2 : 1; }
+// Rows of one row group (a workgroup's register-resident rows).
+constexpr int tri_rows(int ks, int ksc, int nj) { return 16 * kTriWaves * tri_na(ks, ksc, nj); }
 
 // Launch one instantiation; false if (ks, nj, ksc) has none.
 bool launch_grad_tri_matern(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st);

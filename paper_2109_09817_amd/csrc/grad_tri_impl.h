@@ -15,10 +15,10 @@ struct TriChunk {
   static constexpr int kC = 2 * KSC * 64;
   static constexpr int kG = 2 * (2 * NJ) * 64;
   static constexpr int kAll = kDist + kC + kG;
-  static constexpr int kPerThread = (kAll + 64 * kTriWaves - 1) / (64 * kTriWaves);
+  static constexpr int kPerThread = (kAll + 64 * kTriWaves - 1) / (64 * kTriWaves);  // units per wave
 };
 
-template <int KS, int KSC, int NJ, int KIND>
+template <int KS, int KSC, int NJ, int NA, int KIND>
 __global__ __launch_bounds__(64 * kTriWaves, 1) void grad_tri_bf16x3_kernel(GradTriArgs a) {
   constexpr int NG = 2 * NJ;
   using TC = TriChunk<KS, KSC, NJ>;
@@ -30,149 +30,179 @@ __global__ __launch_bounds__(64 * kTriWaves, 1) void grad_tri_bf16x3_kernel(Grad
   const int g = lane >> 4;
   const int c16 = lane & 15;
   const int2 unit = a.units[blockIdx.x];
-  const int64_t ar = (int64_t)unit.x * kTriRows + 16 * wave;  // first row of this wave's block
-  const int64_t ablk = ar / 16;
+  const int64_t ablk0 = ((int64_t)unit.x * kTriWaves + wave) * NA;  // this wave's first 16-row block
   const int64_t c_begin = unit.y;
   const int64_t c_lim = (c_begin / a.cps + 1) * a.cps;
   const int64_t c_end = c_lim < a.nchunks ? c_lim : a.nchunks;
 
-  bf16x8 A[KS], CA[KSC];
+  bf16x8 A[NA][KS], CA[NA][KSC];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) A[ks] = a.xc[(ablk * KS + ks) * 64 + lane];
+  for (int ab = 0; ab < NA; ++ab) {
 #pragma unroll
-  for (int q = 0; q < KSC; ++q) CA[q] = a.ca[(ablk * KSC + q) * 64 + lane];
+    for (int ks = 0; ks < KS; ++ks) A[ab][ks] = a.xc[((ablk0 + ab) * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < KSC; ++q) CA[ab][q] = a.ca[((ablk0 + ab) * KSC + q) * 64 + lane];
+  }
 
-  f32x4 acc[NG];
+  f32x4 acc[NA][NG];
+  float racc[NA];
 #pragma unroll
-  for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float racc = 0.f, sfacc = 0.f;
+  for (int ab = 0; ab < NA; ++ab) {
+    racc[ab] = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  float sfacc = 0.f;
   double g64[NJ];
 #pragma unroll
   for (int cb = 0; cb < NJ; ++cb) g64[cb] = 0.0;
   double sf64 = 0.0;
 
-  bf16x8 pre[TC::kPerThread];
-  auto fetch = [&](int64_t ch) {
+  // Copy chunk ch into stage[buf] with direct global-to-LDS loads: each wave
+  // moves whole 64-lane units (16 bytes per lane, lane-contiguous in LDS), and
+  // the unit boundaries of the three streams are multiples of 64 lanes, so the
+  // source stream is uniform over the wave.  Completion is awaited (vmcnt) and
+  // published by the barrier that ends the iteration.
+  auto fetch = [&](int64_t ch, int buf) {
 #pragma unroll
     for (int r = 0; r < TC::kPerThread; ++r) {
-      const int u = tid + 64 * kTriWaves * r;
-      if (u < TC::kDist) {
-        pre[r] = a.xr[(2 * ch * KS) * 64 + u];
-      } else if (u < TC::kDist + TC::kC) {
-        pre[r] = a.cb[(2 * ch * KSC) * 64 + (u - TC::kDist)];
-      } else if (u < TC::kAll) {
-        pre[r] = a.gv[(ch * NG * 2) * 64 + (u - TC::kDist - TC::kC)];
+      const int ub = 64 * (wave + kTriWaves * r);  // first unit slot of this wave
+      if (ub < TC::kAll) {
+        const bf16x8* src;
+        if (ub < TC::kDist) {
+          src = a.xr + (2 * ch * KS) * 64 + ub;
+        } else if (ub < TC::kDist + TC::kC) {
+          src = a.cb + (2 * ch * KSC) * 64 + (ub - TC::kDist);
+        } else {
+          src = a.gv + (ch * NG * 2) * 64 + (ub - TC::kDist - TC::kC);
+        }
+        __builtin_amdgcn_global_load_lds((const void*)(src + lane),
+                                         (__attribute__((address_space(3))) void*)&stage[buf][ub], 16, 0, 0);
       }
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < TC::kPerThread; ++r) {
-      const int u = tid + 64 * kTriWaves * r;
-      if (u < TC::kAll) stage[buf][u] = pre[r];
     }
   };
   // Fold the FP32 window into the FP64 partials of g_j (j = 16 cb + c16).
   auto flush = [&]() {
-    float rf = racc;  // row sums of P: lane holds row ar + c16 over 8 of the points
-    rf += __shfl_xor(rf, 16, 64);
-    rf += __shfl_xor(rf, 32, 64);
-    double Ri[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Ri[i] = (double)__shfl(rf, 4 * g + i, 64);
+    for (int ab = 0; ab < NA; ++ab) {
+      const int64_t ar = (ablk0 + ab) * 16;
+      float rf = racc[ab];  // row sums of P: lane holds row ar + c16 over 8 of the points
+      rf += __shfl_xor(rf, 16, 64);
+      rf += __shfl_xor(rf, 32, 64);
+      double Ri[4];
 #pragma unroll
-    for (int cb = 0; cb < NJ; ++cb) {
-      const int j = 16 * cb + c16;
-      if (j < a.d) {
-        const double m = a.mu[j], s = a.inv_ell[j];
+      for (int i = 0; i < 4; ++i) Ri[i] = (double)__shfl(rf, 4 * g + i, 64);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t row = ar + 4 * g + i;
-          if (row < a.n) {
-            const double x = (a.X[row * a.d + j] - m) * s;
-            g64[cb] += x * x * Ri[i] - 2.0 * x * (double)acc[cb][i] + (double)acc[NJ + cb][i];
+      for (int cb = 0; cb < NJ; ++cb) {
+        const int j = 16 * cb + c16;
+        if (j < a.d) {
+          const double m = a.mu[j], s = a.inv_ell[j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t row = ar + 4 * g + i;
+            if (row < a.n) {
+              const double x = (a.X[row * a.d + j] - m) * s;
+              g64[cb] += x * x * Ri[i] - 2.0 * x * (double)acc[ab][cb][i] + (double)acc[ab][NJ + cb][i];
+            }
           }
         }
       }
+      racc[ab] = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     sf64 += (double)sfacc;
-#pragma unroll
-    for (int nb = 0; nb < NG; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    racc = 0.f;
     sfacc = 0.f;
   };
 
-  fetch(c_begin);
-  stash(0);
+  fetch(c_begin, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int window = 0;
   for (int64_t ch = c_begin; ch < c_end; ++ch) {
     const int cur = (int)((ch - c_begin) & 1);
     const bool more = ch + 1 < c_end;
-    if (more) fetch(ch + 1);
+    if (more) fetch(ch + 1, cur ^ 1);
     const int64_t b0 = ch * 32;
-    if (b0 + 31 > ar) {  // the tile holds some pair b > a
-      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
-      f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
+    if (b0 + 31 > ablk0 * 16) {  // the first block's tile holds some pair b > a
+      bf16x8 B0[KS], B1[KS];  // distance fragments, shared by the NA blocks
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][ks * 64 + lane], A[ks], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][(KS + ks) * 64 + lane], A[ks], s1, 0, 0, 0);
+        B0[ks] = stage[cur][ks * 64 + lane];
+        B1[ks] = stage[cur][(KS + ks) * 64 + lane];
       }
+      bf16x8 H[NA], L[NA];
+      bool live[NA];
 #pragma unroll
-      for (int q = 0; q < KSC; ++q) {
-        q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[q], q0, 0, 0, 0);
-        q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + (KSC + q) * 64 + lane], CA[q], q1, 0,
-                                                     0, 0);
-      }
-      if (b0 < ar + 16) {  // straddles the block: keep b > a only
-        const int64_t am = ar + c16;
+      for (int ab = 0; ab < NA; ++ab) {
+        const int64_t ar = (ablk0 + ab) * 16;
+        live[ab] = b0 + 31 > ar;
+        if (!live[ab]) continue;
+        f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (b0 + 4 * g + i <= am) q0[i] = 0.f;
-          if (b0 + 16 + 4 * g + i <= am) q1[i] = 0.f;
+        for (int ks = 0; ks < KS; ++ks) {
+          s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
+          s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
         }
-      }
-      f32x8 pv;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float S = __builtin_fabsf(k < 4 ? s0[k] : s1[k - 4]);
-        const float cs = k < 4 ? q0[k] : q1[k - 4];
-        float m, psi;
-        if constexpr (KIND == GP_MATERN52) {
-          const float u = __builtin_amdgcn_sqrtf(S);
-          const float e = __builtin_amdgcn_exp2f(-u);
-          psi = __builtin_fmaf(u, kMaternC1, 1.0f) * e;       // (1 + sqrt5 r) e^{-sqrt5 r}
-          m = __builtin_fmaf(kMaternC2 * S, e, psi);          // (1 + sqrt5 r + 5r^2/3) e^{-sqrt5 r}
-        } else {
-          m = __builtin_amdgcn_exp2f(-S);
-          psi = m;
+        for (int q = 0; q < KSC; ++q) {  // C fragments re-read per block (register budget)
+          q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[ab][q], q0, 0, 0, 0);
+          q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + (KSC + q) * 64 + lane], CA[ab][q], q1,
+                                                       0, 0, 0);
         }
-        const float p = psi * cs;
-        pv[k] = p;
-        racc += p;
-        sfacc = __builtin_fmaf(m, cs, sfacc);
+        if (b0 < ar + 16) {  // straddles the block: keep b > a only
+          const int64_t am = ar + c16;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (b0 + 4 * g + i <= am) q0[i] = 0.f;
+            if (b0 + 16 + 4 * g + i <= am) q1[i] = 0.f;
+          }
+        }
+        f32x8 pv;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float S = __builtin_fabsf(k < 4 ? s0[k] : s1[k - 4]);
+          const float cs = k < 4 ? q0[k] : q1[k - 4];
+          float m, psi;
+          if constexpr (KIND == GP_MATERN52) {
+            const float u = __builtin_amdgcn_sqrtf(S);
+            const float e = __builtin_amdgcn_exp2f(-u);
+            psi = __builtin_fmaf(u, kMaternC1, 1.0f) * e;  // (1 + sqrt5 r) e^{-sqrt5 r}
+            m = __builtin_fmaf(kMaternC2 * S, e, psi);     // (1 + sqrt5 r + 5r^2/3) e^{-sqrt5 r}
+          } else {
+            m = __builtin_amdgcn_exp2f(-S);
+            psi = m;
+          }
+          const float p = psi * cs;
+          pv[k] = p;
+          racc[ab] += p;
+          sfacc = __builtin_fmaf(m, cs, sfacc);
+        }
+        split_bf16x8(pv, H[ab], L[ab]);
       }
-      bf16x8 H, L;
-      split_bf16x8(pv, H, L);
 #pragma unroll
       for (int nb = 0; nb < NG; ++nb) {
         const bf16x8 Gh = stage[cur][TC::kDist + TC::kC + (2 * nb) * 64 + lane];
         const bf16x8 Gl = stage[cur][TC::kDist + TC::kC + (2 * nb + 1) * 64 + lane];
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gh, acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, Gl, acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, Gh, acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int ab = 0; ab < NA; ++ab) {
+          if (!live[ab]) continue;
+          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gh, acc[ab][nb], 0, 0, 0);
+          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gl, acc[ab][nb], 0, 0, 0);
+          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L[ab], Gh, acc[ab][nb], 0, 0, 0);
+        }
       }
     }
     if (++window == kTriFlush || !more) {
       flush();
       window = 0;
     }
-    if (more) stash(cur ^ 1);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 
-  // unit partial: sum over the 16 rows of every wave, then over the waves
+  // unit partial: sum over the rows of every wave, then over the waves
 #pragma unroll
   for (int cb = 0; cb < NJ; ++cb) {
     double v = g64[cb];
@@ -195,7 +225,8 @@ __global__ __launch_bounds__(64 * kTriWaves, 1) void grad_tri_bf16x3_kernel(Grad
 
 template <int KS, int NJ, int KSC, int KIND>
 static void tri_launch(unsigned units, const GradTriArgs& a, hipStream_t st) {
-  grad_tri_bf16x3_kernel<KS, KSC, NJ, KIND><<<units, 64 * kTriWaves, 0, st>>>(a);
+  constexpr int NA = tri_na(KS, KSC, NJ);
+  grad_tri_bf16x3_kernel<KS, KSC, NJ, NA, KIND><<<units, 64 * kTriWaves, 0, st>>>(a);
 }
 
 template <int KS, int NJ, int KIND>
