@@ -54,6 +54,11 @@ def main():
     ap.add_argument("--profile-kmm", type=int, default=0, metavar="K",
                     help="profiling mode: a 1 GiB device copy (traffic calibration) then K products "
                          "K_hat V at n = 917,504, t = 16 (BF16x3), and exit")
+    ap.add_argument("--profile-grad", type=int, default=0, metavar="K",
+                    help="profiling mode: K gradient sweeps gp_kmm_grad at n = 917,504, t = 16 (BF16x3), and exit")
+    ap.add_argument("--fit-c4", type=int, default=0, metavar="K",
+                    help="training mode: K Adam steps (lr 0.05 on log theta, start l = 1, s_f = 1, "
+                         "sigma^2 = 1e-2) on the n = 262,144, d = 48 model with t = 32 probes, and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -75,6 +80,12 @@ def main():
 
     if args.profile_kmm:
         profile_kmm(args, gp, synth, torch, dev)
+        return
+    if args.profile_grad:
+        profile_grad(args, gp, synth, torch, dev, np)
+        return
+    if args.fit_c4:
+        fit_c4(args, synth, torch, dev, np)
         return
 
     names = [("c3o", 917504), ("c3d", 131072)]
@@ -259,6 +270,47 @@ def profile_kmm(args, gp, synth, torch, dev):
     gp.profile_read(reset=True)
     print(json.dumps({"profile_kmm": {"copy_bytes": 2 * a.numel() * 8, "launch_ms": [r[3] for r in recs]}}),
           flush=True)
+
+
+def profile_grad(args, gp, synth, torch, dev, np):
+    """K hyperparameter-gradient sweeps on the n = 917,504 model, t = 16, to read counters on."""
+    p = synth.make_problem("c3o")
+    X = torch.from_numpy(p.X).to(dev)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    U = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 4)).to(dev)
+    W = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 5)).to(dev)
+    w = np.concatenate([[0.5], np.full(15, -0.5 / 15)])
+    ms = []
+    for _ in range(args.profile_grad):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = gp.kmm_grad(k, X, U, W, w, precision="bf16x3")
+        ms.append((time.perf_counter() - t0) * 1e3)
+    print(json.dumps({"profile_grad": {"call_ms": ms, "grad0": float(g[0])}}), flush=True)
+
+
+def fit_c4(args, synth, torch, dev, np):
+    """Hyperparameter training on the gradient configuration: Adam on log theta through autograd.MLL."""
+    from paper_2109_09817_amd import autograd as ag
+    p = synth.make_problem("c4")
+    X = torch.from_numpy(p.X).to(dev)
+    y = torch.from_numpy(p.y).to(dev)
+    d = p.X.shape[1]
+    start = np.concatenate([np.zeros(d), [0.0, math.log(1e-2)]])
+    cfg = synth.CONFIGS["c4"]
+
+    def progress(s, r):
+        log(f"step {s}: mll {r.mll[-1]:.6e} iters {r.iters[-1]} {r.seconds[-1]:.3f} s")
+
+    res = ag.fit(X, y, start, steps=args.fit_c4, lr=0.05, probes=cfg.probes, rank=cfg.rank,
+                 max_iter=cfg.max_iter, tol=cfg.tol, seed=cfg.seed, callback=progress)
+    th = np.exp(res.log_theta)
+    print(json.dumps({"fit_c4": {
+        "n": int(p.X.shape[0]), "d": d, "probes": cfg.probes, "steps": args.fit_c4,
+        "s_per_step": float(np.mean(res.seconds[1:] if len(res.seconds) > 1 else res.seconds)),
+        "first_step_s": res.seconds[0], "mll": res.mll, "mbcg_iters": res.iters,
+        "final": {"lengthscale_min": float(th[:d].min()), "lengthscale_max": float(th[:d].max()),
+                  "outputscale": float(th[d]), "noise": float(th[d + 1])}}}), flush=True)
 
 
 def serve_leg(args, gp, synth, torch, dev, np):

@@ -10,7 +10,7 @@
 // Each unordered pair is evaluated once: half the distance products, half the
 // kernel evaluations of the full-matrix sweep.
 //
-// Work unit: a row group of 128 or 256 rows a (8 waves x one or two 16-row
+// Work unit: a row group of 64 or 128 rows a (4 waves x one or two 16-row
 // blocks, held in registers) against a range of 32-point chunks b at or after the group's own
 // first chunk; pairs with b <= a inside a chunk that straddles a block are
 // masked.  Per (16 rows) x (32 points) tile, on the BF16 matrix cores:
@@ -21,7 +21,7 @@
 // Every 32 chunks the FP32 sums are folded into per-lane FP64 partials of
 //   g_j += sum_a x~_aj^2 R_a - 2 x~_aj Q_aj + T_aj,  R_a = sum_b P_ab.
 // The b-side fragments of each chunk are staged in LDS, double-buffered, and
-// shared by the 8 waves.
+// shared by the workgroup's waves.
 #pragma once
 
 #include "internal.h"
@@ -47,7 +47,10 @@ struct GradTriArgs {
   double* part;         // per unit: g_1..g_d, g_{s_f} (unscaled)
 };
 
-constexpr int kTriWaves = 8;
+// Waves per workgroup.  Two 4-wave workgroups share a CU: the per-chunk
+// barrier then keeps only half the CU's waves in step, and the other
+// workgroup's waves fill the matrix cores while these run their VALU phase.
+constexpr int kTriWaves = 4;
 constexpr int kTriFlush = 32;  // chunks per FP32 accumulation window
 
 // 16-row blocks per wave: two while they fit in 256 VGPRs without spilling

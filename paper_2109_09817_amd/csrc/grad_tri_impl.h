@@ -19,11 +19,12 @@ struct TriChunk {
 };
 
 template <int KS, int KSC, int NJ, int NA, int KIND>
-__global__ __launch_bounds__(64 * kTriWaves, 1) void grad_tri_bf16x3_kernel(GradTriArgs a) {
+__global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(GradTriArgs a) {
   constexpr int NG = 2 * NJ;
   using TC = TriChunk<KS, KSC, NJ>;
   __shared__ bf16x8 stage[2][TC::kAll];
-  __shared__ double red[kTriWaves][GP_MAX_D + 1];
+  static_assert(sizeof(stage) >= sizeof(double) * kTriWaves * (GP_MAX_D + 1), "reduction scratch");
+  double(*red)[GP_MAX_D + 1] = reinterpret_cast<double(*)[GP_MAX_D + 1]>(&stage[0][0]);  // after the loop only
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
