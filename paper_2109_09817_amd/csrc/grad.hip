@@ -376,11 +376,15 @@ static int64_t tri_units(int64_t n, int64_t rows, int64_t nchunks, int64_t cps, 
   return count;
 }
 
-static int64_t tri_cps(int64_t n, int64_t rows, int64_t nchunks) {
+// Unit length in chunks: enough units to fill the GPU, and short enough that
+// one chunk segment's staged data (chunk_bytes each) stays within an XCD's
+// 4 MB L2 while the workgroups streaming it drift apart.
+static int64_t tri_cps(int64_t n, int64_t rows, int64_t nchunks, int64_t chunk_bytes) {
   const int64_t groups = (n + rows - 1) / rows;
   const int64_t f_last = (groups - 1) * (rows / 32);
   const int64_t work = groups * nchunks - (f_last + rows / 32) * groups / 2;  // chunk visits, approximately
-  return std::min<int64_t>(1024, std::max<int64_t>(32, work / 4096));
+  const int64_t fit_l2 = (int64_t)(3 << 20) / chunk_bytes;
+  return std::min<int64_t>(1024, std::max<int64_t>(32, std::min(work / 4096, fit_l2)));
 }
 
 // Column blocks of [x~ | 1 | x~^2] of the FP32 form, sized for the instantiated
@@ -411,7 +415,7 @@ static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
     g.ncb = 2 * g.nj;
     g.rows = g.ksc > 0 ? tri_rows(g.ks, g.ksc, g.nj) : 16 * kTriWaves;
     g.mpad = (n + g.rows - 1) / g.rows * g.rows;
-    g.cps = tri_cps(n, g.rows, g.nchunks);
+    g.cps = tri_cps(n, g.rows, g.nchunks, (int64_t)(2 * g.ks + 2 * g.ksc + 2 * g.ncb) * 64 * 16);
     g.nunits = tri_units(n, g.rows, g.nchunks, g.cps, nullptr);
   } else {
     g.ksc = (t + 15) / 16;
