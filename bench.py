@@ -41,6 +41,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+SWEEP_COUNTERS = os.path.join(ROOT, "profiles", "sweep_bf16x3_n917504_t16_counters.md")
+
+
+def measured_traffic():
+    """HBM bytes per n = 917,504 sweep launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel), or None when the sweep's sources have changed since."""
+    import hashlib
+    try:
+        text = open(SWEEP_COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(l.split(" = ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "sources_sha256")))
+    if "sources_sha256" not in vals:
+        return None
+    digest, files = vals["sources_sha256"].split("  (", 1)
+    h = hashlib.sha256()
+    for f in files.rstrip(")").split(", "):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return float(vals["traffic_bytes_per_launch"]) if h.hexdigest() == digest.strip() else None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,10 +238,10 @@ def main():
             blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         except Exception:
             blas = None
-        cpu = {"value": fl / (t5 - t4) / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": fl / (t5 - t4) / 1e12, "unit": "TFLOP/s", "cores": blas or 1, "kind": "oracle",
                "sample": f"FP64 oracle K_hat V for {R} sampled rows of the n=917,504 model (t={t_cols}); "
-                         f"{t5 - t4:.1f} s; the oracle's distances (scipy cdist) run on one thread, "
-                         f"its product on {blas} BLAS threads of {os.cpu_count()} host cores"}
+                         f"{t5 - t4:.1f} s; the oracle's product runs on {blas} BLAS threads of "
+                         f"{os.cpu_count()} host cores, its distances (scipy cdist) on one of them"}
         log(f"cpu baseline: {cpu['value']:.3e} TFLOP/s in {t5 - t4:.1f}s")
 
     if not args.no_serve:
@@ -242,7 +264,7 @@ def main():
                                "d=48, Matern-5/2 ARD, sigma^2=1e-3, [y | 15 probes], rank-100 pivoted Cholesky, "
                                "mBCG tol 1e-6", "n": [917504, 131072], "d": 48, "t": t_cols},
         "roofline": {"bound": "mfma", "achieved": kernel_tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": kernel_tflops / PEAK_BF16_TFLOPS if kernel_tflops else None, "traffic": None,
+                     "frac": kernel_tflops / PEAK_BF16_TFLOPS if kernel_tflops else None, "traffic": measured_traffic(),
                      "kernel": "sweep_bf16x3_kernel<5,1,MATERN52> at n=917,504, t=16",
                      "work": "2 n^2 (d + t) = 1.080e14 nominal flops per launch", "avg_launch_ms": big_ms},
         "cpu_baseline": cpu,
