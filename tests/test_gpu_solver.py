@@ -229,6 +229,29 @@ def test_kmm_grad_matches_oracle(n, d, t, kind, prec):
     assert err <= (1e-5 if prec == "fp32" else 1e-4)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,t", [(1, 1), (2, 2), (33, 1), (129, 3)])
+def test_kmm_grad_tiny_and_ragged(n, t, prec):
+    """One point (no pairs: every lengthscale entry is exactly zero), two points, and sizes that end
+    inside the first chunk / row group of the sweeps."""
+    from paper_2109_09817_amd import gp
+    X, y, th0 = _problem(max(n, 2), 5, True)
+    X = np.ascontiguousarray(X[:n])
+    th = ok.Theta(th0.ell, 0.9, 5e-3)
+    rng = np.random.default_rng(100 + n)
+    U = rng.standard_normal((n, t))
+    W = rng.standard_normal((n, t))
+    w = rng.standard_normal(t)
+    got = gp.kmm_grad(_gk(th), dev(X), dev(U.T), dev(W.T), w, precision=prec)
+    ref = bilinear_forms(X, th, U, W, w)
+    scale = bilinear_forms(X, th, np.abs(U), np.abs(W), np.abs(w))
+    if n == 1:
+        assert np.all(got[:5] == 0.0)
+    err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+    log(f"kmm_grad tiny {prec} n={n} t={t}: max err / term scale {err:.2e}")
+    assert err <= (1e-5 if prec == "fp32" else 1e-4)
+
+
 def test_lanczos_cache_and_predict_match_oracle():
     import torch
     from paper_2109_09817_amd import gp
