@@ -72,6 +72,9 @@ extern "C" {
 #define GP_OP_PREDICT 6
 #define GP_OP_LANCZOS 7
 #define GP_OP_PREDICT_RUN 8
+#define GP_OP_NYSTROM 9
+#define GP_OP_NYSTROM_APPLY 10
+#define GP_OP_BCG 11
 
 /*
  * ARD stationary kernel with r^2 = sum_j ((x_j - z_j) / l_j)^2 (Sec. 2.2;
@@ -155,8 +158,9 @@ int gp_kmm(const gp_kernel* kern, int32_t precision,
  * and dK_hat/dlog sigma^2 = sigma^2 I.  Tiles are recomputed, never stored.
  * U, W: device n x t with ldu = ldw = n, t <= 64, d <= 64; colw: host, t
  * weights; grad: host, d + 2 values.  precision selects the matrix-core form
- * of the tile products (distances, C = U diag(w) W^T and psi (.) C times
- * [x~ | 1 | x~^2]) as for gp_kmm.  Synchronous.
+ * of the tile products (distances, C = U diag(w) W^T and psi (.) C times the
+ * columns [x~ | x~^2]) as for gp_kmm; the BF16X3 form visits each unordered
+ * pair a < b once with C + C^T.  Synchronous.
  */
 int gp_kmm_grad(const gp_kernel* kern, int32_t precision,
                 const double* X, int64_t n,
@@ -275,6 +279,58 @@ int gp_predict_run(const gp_kernel* kern, int32_t precision, const void* model, 
  * beta[j*stride].  Returns GP_ENOTPD if T is not positive definite.
  */
 int gp_lanczos_quadrature(const double* alpha, const double* beta, int32_t J, int32_t stride, double* out);
+
+/*
+ * gp_nystrom_precond - the AltBBMM preconditioner (Sec. 3.2, Sec. 4): the
+ * Nystrom approximation over r landmark rows M,
+ *   P = K_XM K_MM^{-1} K_MX + sigma^2 I,
+ * in the factored form of its inverse square root
+ *   P^{-1/2} = sigma^{-1} I + K_XM H K_MX.
+ * landmarks: host, r distinct indices in [0, n) (the paper draws them at
+ * random; pass the draw).  KXM: device, n x r column-major (ld = n), the
+ * kernel columns K(X, X[M]) in FP64.  H: device, r x r (symmetric).
+ * Requires sigma^2 > 0 and 1 <= r <= min(n, 1024).  Errors: GP_EINVAL (sizes,
+ * repeated or out-of-range landmarks), GP_ENOTPD (K_MM not positive definite),
+ * GP_ENONFINITE, GP_EWORKSPACE, GP_EHIP.  Synchronous (the r x r factorisation
+ * and eigendecomposition run on the host).
+ * Workspace: gp_workspace_bytes(GP_OP_NYSTROM, n, 0, d, 0, r, any precision).
+ */
+int gp_nystrom_precond(const gp_kernel* kern, const double* X, int64_t n,
+                       const int64_t* landmarks, int32_t r, double* KXM, double* H,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_nystrom_apply - Y = P^{-1/2} V = sigma^{-1} V + KXM (H (KXM^T V)) for a
+ * device n x s block V (column-major, ld = n), s <= 64; Y likewise (may equal
+ * V).  KXM, H from gp_nystrom_precond; noise = its sigma^2.  Asynchronous.
+ * Workspace: gp_workspace_bytes(GP_OP_NYSTROM_APPLY, n, 0, 1, s, r, any precision).
+ */
+int gp_nystrom_apply(const double* KXM, const double* H, int64_t n, int32_t r, double noise,
+                     const double* V, int32_t s, double* Y,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_bcg - AltBBMM solve (Sec. 3.1 block CG, Sec. 3.2): block conjugate
+ * gradients on the symmetrically preconditioned system
+ *   P^{-1/2} K_hat P^{-1/2} Z = P^{-1/2} B,   W = P^{-1/2} Z  (= K_hat^{-1} B),
+ * with P the Nystrom preconditioner of gp_nystrom_precond (r > 0) or the
+ * identity (r = 0; KXM, H ignored).  Iteration (O'Leary): Q = A D,
+ * alpha = (D^T Q)^{-1} R^T R, Z += D alpha, R -= Q alpha,
+ * beta = (R_old^T R_old)^{-1} R^T R, D = R + D beta.  Stops when every column's
+ * relative residual ||R_c|| / ||P^{-1/2} B_c|| <= tol (the paper: 1e-6 for all
+ * s = 50 columns); GP_WNOCONV after max_iter.  K_hat products in `precision`
+ * (as gp_kmm); recurrences, preconditioner and the s x s solves in FP64.
+ * B: device n x s (ldb >= n), nonzero columns, s <= 64.  W: device n x s
+ * (ldw >= n).  iters: host, the iterations run.  relres: host, s final
+ * relative residuals.  GP_ENOTPD on block breakdown (D^T A D or R^T R not
+ * positive definite).  Synchronises twice per iteration.
+ * Workspace: gp_workspace_bytes(GP_OP_BCG, n, 0, d, s, r, precision).
+ */
+int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
+           const double* KXM, const double* H, int32_t r,
+           const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
+           double* W, int64_t ldw, int32_t* iters, double* relres,
+           void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gp_workspace_bytes - device scratch needed by one call of `op`

@@ -29,6 +29,9 @@ GP_OP_MLL = 5
 GP_OP_PREDICT = 6
 GP_OP_LANCZOS = 7
 GP_OP_PREDICT_RUN = 8
+GP_OP_NYSTROM = 9
+GP_OP_NYSTROM_APPLY = 10
+GP_OP_BCG = 11
 
 
 class GpKernel(C.Structure):
@@ -82,6 +85,11 @@ PROTOTYPES = {
     "gp_predict_prepare": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _SZ, _P]),
     "gp_predict_run": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _I32, _P, _I64, _P, _P, _P, _SZ, _P]),
     "gp_lanczos_quadrature": (C.c_int, [C.POINTER(_D), C.POINTER(_D), _I32, _I32, C.POINTER(_D)]),
+    "gp_nystrom_precond": (C.c_int, [C.POINTER(GpKernel), _P, _I64, C.POINTER(C.c_int64), _I32, _P, _P,
+                                     _P, _SZ, _P]),
+    "gp_nystrom_apply": (C.c_int, [_P, _P, _I64, _I32, _D, _P, _I32, _P, _P, _SZ, _P]),
+    "gp_bcg": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _I64, _I32, _I32, _D, _P, _I64,
+                         C.POINTER(_I32), C.POINTER(_D), _P, _SZ, _P]),
     "gp_workspace_bytes": (C.c_size_t, [_I32, _I64, _I64, _I32, _I32, _I32, _I32]),
     "gp_profile_enable": (C.c_int, [_I32]),
     "gp_profile_read": (C.c_int, [C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), _I32]),

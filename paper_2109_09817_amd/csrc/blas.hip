@@ -509,6 +509,16 @@ hipError_t atb(const double* A, int pa, const double* B, int qb, int64_t n, doub
   return hipGetLastError();
 }
 
+hipError_t atb_n(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
+                 int64_t nblk, hipStream_t st) {
+  const RowSplit rs = row_split(n, nblk);
+  dim3 grid((unsigned)rs.nblk, (unsigned)((pa + 63) / 64), (unsigned)((qb + 63) / 64));
+  atb_partial_kernel<<<grid, 256, 0, st>>>(A, pa, B, qb, n, rs.rows_per_blk, partial);
+  const int64_t pq = (int64_t)pa * qb;
+  atb_reduce_kernel<<<blocks_for(pq), kThreads, 0, st>>>(partial, rs.nblk, pq, out);
+  return hipGetLastError();
+}
+
 hipError_t precond_apply(const Precond& pc, const double* R, double* Z, int64_t n, int s, double* Y,
                          double* partial, hipStream_t st) {
   if (pc.rank == 0) {

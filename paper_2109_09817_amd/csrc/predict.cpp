@@ -13,6 +13,9 @@ size_t pivchol_ws_bytes(int64_t n, int k);
 size_t mbcg_ws_bytes(int precision, int d, int64_t n, int s, int rank);
 size_t mll_ws_bytes(int precision, int d, int64_t n, int t, int k);
 size_t grad_ws_bytes(int precision, int d, int64_t n, int t);
+size_t nystrom_ws_bytes(int d, int64_t n, int r);
+size_t nystrom_apply_ws_bytes(int64_t n, int r, int s);
+size_t bcg_ws_bytes(int precision, int d, int64_t n, int r, int s);
 
 constexpr int kMaxCache = 4095;  // kc + 1 <= 4096 product columns
 
@@ -198,6 +201,15 @@ extern "C" size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d
     case GP_OP_LANCZOS:
       if (k < 1) return 0;
       return lanczos_ws_bytes(precision, d, n, k);
+    case GP_OP_NYSTROM:
+      if (k < 1 || k > 1024 || k > n) return 0;
+      return nystrom_ws_bytes(d, n, k);
+    case GP_OP_NYSTROM_APPLY:
+      if (k < 1 || k > 1024 || k > n || t < 1 || t > 64) return 0;
+      return nystrom_apply_ws_bytes(n, k, t);
+    case GP_OP_BCG:
+      if (k < 0 || k > 1024 || k > n || t < 1 || t > 64) return 0;
+      return bcg_ws_bytes(precision, d, n, k, t);
     default:
       return 0;
   }

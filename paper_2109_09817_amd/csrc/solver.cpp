@@ -47,7 +47,7 @@ size_t mbcg_ws_bytes(int precision, int d, int64_t n, int s, int rank) {
 
 // ------------------------------------------------------------- pivoted Cholesky
 
-static bool host_cholesky(std::vector<double>& A, int k) {
+bool host_cholesky(std::vector<double>& A, int k) {
   // in place, lower, row-major k x k (A symmetric)
   for (int j = 0; j < k; ++j) {
     double v = A[(size_t)j * k + j];

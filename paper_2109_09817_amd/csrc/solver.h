@@ -61,6 +61,9 @@ hipError_t coldot(const double* A, const double* B, int64_t n, int s, double* ou
 size_t atb_partial_doubles(int64_t n, int pa, int qb);
 hipError_t atb(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
                hipStream_t st);
+// atb with the row split into (at most) nblk blocks; partial holds nblk * pa * qb doubles.
+hipError_t atb_n(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
+                 int64_t nblk, hipStream_t st);
 // Z = P^{-1} R for an n x s block.  Y: rank x s scratch; partial: atb scratch.
 hipError_t precond_apply(const Precond& pc, const double* R, double* Z, int64_t n, int s, double* Y,
                          double* partial, hipStream_t st);
@@ -95,5 +98,12 @@ bool lanczos_log_quadrature(const double* alpha, const double* beta, int J, int 
 // Host: eigenvalues (ascending not guaranteed) and first eigenvector components of a
 // symmetric tridiagonal matrix (diag a[0..n-1], off-diagonal b[0..n-2]).
 bool tridiag_eig_first(int n, double* a, double* b, double* z);
+// Host: in-place lower Cholesky factor of the symmetric k x k matrix A (row-major);
+// false if A is not positive definite.
+bool host_cholesky(std::vector<double>& A, int k);
+// Host: all eigenpairs of the dense symmetric n x n matrix A (row-major, destroyed):
+// A = Q diag(w) Q^T, Q row-major with the eigenvectors as columns.  False if the
+// iteration does not converge.
+bool sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& Q);
 
 }  // namespace gpk

@@ -224,6 +224,80 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, probes: int, ra
     return MllResult(float(mll.value), g if with_grad else None, inf, rc)
 
 
+@dataclasses.dataclass
+class Nystrom:
+    """AltBBMM preconditioner: P^{-1/2} = sigma^{-1} I + K_XM H K_MX over landmark rows."""
+
+    KXM: torch.Tensor       # (r, n): row j = kernel column K(X, x_{M_j})
+    H: torch.Tensor         # (r, r)
+    landmarks: np.ndarray
+    noise: float
+
+    @property
+    def rank(self) -> int:
+        return self.KXM.shape[0]
+
+
+def nystrom_precond(kern: Kernel, X: torch.Tensor, landmarks) -> Nystrom:
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    M = np.ascontiguousarray(np.asarray(landmarks, dtype=np.int64))
+    r = M.shape[0]
+    KXM = torch.empty((r, n), dtype=torch.float64, device=X.device)
+    H = torch.empty((r, r), dtype=torch.float64, device=X.device)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM, n, 0, kern.d, 0, r, _lib.GP_PREC_FP32), X.device)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_nystrom_precond(C.byref(ks), X.data_ptr(), n, M.ctypes.data_as(C.POINTER(C.c_int64)), r,
+                                      KXM.data_ptr(), H.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return Nystrom(KXM, H, M, kern.noise)
+
+
+def nystrom_apply(pc: Nystrom, V: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """P^{-1/2} V for a (s, n) block."""
+    lib = _lib.load()
+    r, n = pc.KXM.shape
+    s = V.shape[0]
+    _need(V, "V", (s, n))
+    if out is None:
+        out = torch.empty_like(V)
+    _need(out, "out", (s, n))
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM_APPLY, n, 0, 1, s, r, _lib.GP_PREC_FP32), V.device)
+    _lib.check(lib.gp_nystrom_apply(pc.KXM.data_ptr(), pc.H.data_ptr(), n, r, pc.noise, V.data_ptr(), s,
+                                    out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(V.device)))
+    return out
+
+
+@dataclasses.dataclass
+class BcgResult:
+    W: torch.Tensor          # (s, n): K_hat^{-1} B
+    iters: int
+    relres: np.ndarray       # (s,)
+    status: int              # GP_OK or GP_WNOCONV
+
+
+def bcg(kern: Kernel, X: torch.Tensor, B: torch.Tensor, max_iter: int, tol: float,
+        pc: Optional[Nystrom] = None, precision="bf16x3") -> BcgResult:
+    """AltBBMM: block CG on P^{-1/2} K_hat P^{-1/2} (P Nystrom, or the identity when pc is None)."""
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    s = B.shape[0]
+    _need(B, "B", (s, n))
+    r = 0 if pc is None else pc.rank
+    W = torch.empty_like(B)
+    p = _prec(precision)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_BCG, n, 0, kern.d, s, r, p), X.device)
+    it = C.c_int32(0)
+    rr = np.zeros(s)
+    ks, _keep = kern.struct()
+    rc = _lib.check(lib.gp_bcg(C.byref(ks), p, X.data_ptr(), n, _ptr(None if pc is None else pc.KXM),
+                               _ptr(None if pc is None else pc.H), r, B.data_ptr(), n, s, max_iter, tol,
+                               W.data_ptr(), n, C.byref(it), rr.ctypes.data_as(C.POINTER(C.c_double)),
+                               ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return BcgResult(W, int(it.value), rr, rc)
+
+
 def lanczos_cache(kern: Kernel, X: torch.Tensor, y: torch.Tensor, kc: int, precision="bf16x3"):
     """Variance cache R (kc, n) with R R^T ~ K_hat^{-1} on the Krylov space of y; returns (R, rank)."""
     lib = _lib.load()

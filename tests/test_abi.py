@@ -95,3 +95,48 @@ def test_workspace_sizes_are_sane(lib):
     # per training point: fragments of both sides + V fragments + FP64 partials, a few hundred bytes
     assert big / 917504 < 1024
     assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, 1000, 0, 500, 16, 0, 1) == 0
+
+
+def test_altbbmm_entry_points_validate_on_the_host(lib):
+    from paper_2109_09817_amd import _lib
+    k, keep = _kernel()
+    fake = 4096  # never dereferenced: validation fails first
+    M = np.array([0, 3, 3], dtype=np.int64)
+    Mp = M.ctypes.data_as(C.POINTER(C.c_int64))
+    # repeated landmark, r > n, landmark out of range, NULL output
+    assert lib.gp_nystrom_precond(C.byref(k), fake, 10, Mp, 3, fake, fake, None, 0, None) == _lib.GP_EINVAL
+    assert b"repeated" in lib.gp_last_error()
+    M2 = np.array([0, 1, 2], dtype=np.int64)
+    M2p = M2.ctypes.data_as(C.POINTER(C.c_int64))
+    assert lib.gp_nystrom_precond(C.byref(k), fake, 2, M2p, 3, fake, fake, None, 0, None) == _lib.GP_EINVAL
+    M3 = np.array([0, 10], dtype=np.int64)
+    assert lib.gp_nystrom_precond(C.byref(k), fake, 10, M3.ctypes.data_as(C.POINTER(C.c_int64)), 2, fake, fake,
+                                  None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_nystrom_precond(C.byref(k), fake, 10, M2p, 3, None, fake, None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_nystrom_precond(C.byref(k), fake, 10, M2p, 3, fake, fake, None, 0, None) == _lib.GP_EWORKSPACE
+    k0, keep0 = _kernel(noise=0.0)
+    assert lib.gp_nystrom_precond(C.byref(k0), fake, 10, M2p, 3, fake, fake, None, 0, None) == _lib.GP_EINVAL
+    # apply: s outside [1, 64], zero noise
+    assert lib.gp_nystrom_apply(fake, fake, 10, 3, 1e-2, fake, 65, fake, None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_nystrom_apply(fake, fake, 10, 3, 0.0, fake, 2, fake, None, 0, None) == _lib.GP_EINVAL
+    # block CG: s, ld, max_iter, tol, missing preconditioner, workspace
+    it = C.c_int32(0)
+    rr = np.zeros(64)
+    rrp = rr.ctypes.data_as(C.POINTER(C.c_double))
+    base = dict(prec=1, n=10, kxm=None, h=None, r=0, ldb=10, s=2, mi=5, tol=1e-6, ldw=10)
+
+    def call(**kw):
+        a = dict(base)
+        a.update(kw)
+        return lib.gp_bcg(C.byref(k), a["prec"], fake, a["n"], a["kxm"], a["h"], a["r"], fake, a["ldb"], a["s"],
+                          a["mi"], a["tol"], fake, a["ldw"], C.byref(it), rrp, None, 0, None)
+
+    assert call(s=0) == _lib.GP_EINVAL and call(s=65) == _lib.GP_EINVAL
+    assert call(ldb=9) == _lib.GP_EINVAL and call(ldw=9) == _lib.GP_EINVAL
+    assert call(mi=0) == _lib.GP_EINVAL and call(tol=-1.0) == _lib.GP_EINVAL
+    assert call(r=3) == _lib.GP_EINVAL  # r > 0 without KXM, H
+    assert call(prec=5) == _lib.GP_EINVAL
+    assert call() == _lib.GP_EWORKSPACE
+    assert lib.gp_workspace_bytes(_lib.GP_OP_BCG, 917504, 0, 48, 50, 512, 1) > 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_BCG, 1000, 0, 48, 65, 0, 1) == 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM, 1000, 0, 48, 0, 1025, 1) == 0

@@ -1,0 +1,112 @@
+"""AltBBMM on the GPU (gp_nystrom_precond, gp_nystrom_apply, gp_bcg) against the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.kernel as ok
+import synth
+from oracle import altbbmm as ab
+from _helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+EPS_PRODUCT = {"bf16x3": 3e-5, "fp32": 2e-6}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _gk(th):
+    from paper_2109_09817_amd import gp
+    return gp.Kernel(th.ell, th.sf, th.noise, "matern52" if th.kind == ok.MATERN52 else "rbf")
+
+
+def _problem(n, noise=1e-3, seed=0, kind=ok.MATERN52):
+    p = synth.make_problem("c2", n=n, cond_variant=True, seed=seed)
+    th = ok.Theta(p.ell, 1.0, noise, kind)
+    return p.X, p.y, th
+
+
+def _landmarks(n, r, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, r, replace=False))
+
+
+@pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
+@pytest.mark.parametrize("r", [1, 37, 300])
+def test_nystrom_matches_oracle(kind, r):
+    from paper_2109_09817_amd import gp
+    n = 1500
+    X, y, th = _problem(n, kind=kind)
+    M = _landmarks(n, r, 7)
+    pc = gp.nystrom_precond(_gk(th), dev(X), M)
+    KXM_ref = ok.kernel(X, X[M], th)
+    e_k = np.abs(host(pc.KXM).T - KXM_ref).max() / np.abs(KXM_ref).max()
+    S_ref = ab.inv_sqrt(ab.nystrom_matrix(X, th, M))
+    V = np.random.default_rng(3).standard_normal((5, n))
+    got = host(gp.nystrom_apply(pc, dev(V)))
+    ref = V @ S_ref  # S symmetric: rows of (S V^T)^T
+    e_a = np.abs(got - ref).max() / (np.abs(V) @ np.abs(S_ref)).max()
+    kmm_cond = np.linalg.cond(KXM_ref[M])
+    log(f"nystrom kind={kind} r={r}: KXM err {e_k:.1e}, P^-1/2 V err {e_a:.1e} (cond K_MM {kmm_cond:.1e})")
+    assert e_k <= 1e-13
+    assert e_a <= max(1e-10, 1e-15 * kmm_cond)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("r", [0, 120])
+def test_bcg_matches_oracle(prec, r):
+    from paper_2109_09817_amd import gp
+    n, s = 1200, 8
+    X, y, th = _problem(n, seed=1)
+    rng = np.random.default_rng(5)
+    B = np.column_stack([y, rng.standard_normal((n, s - 1))])
+    M = _landmarks(n, r, 9) if r else None
+    Kh = ok.khat(X, th)
+    ref = np.linalg.solve(Kh, B)
+    o = ab.altbbmm_solve(X, th, B, M, 1e-6, 400)
+    pc = gp.nystrom_precond(_gk(th), dev(X), M) if r else None
+    res = gp.bcg(_gk(th), dev(X), dev(B.T), 400, 1e-6, pc=pc, precision=prec)
+    W = host(res.W).T
+    ev = np.linalg.eigvalsh(Kh)
+    kappa = ev[-1] / ev[0]
+    err = np.linalg.norm(W - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    bound = max(1e-5, 10 * kappa * max(1e-6, EPS_PRODUCT[prec]))
+    true_res = np.linalg.norm(Kh @ W - B, axis=0) / np.linalg.norm(B, axis=0)
+    log(f"bcg {prec} r={r}: iters gpu {res.iters} oracle {o['iters']}, relres max {res.relres.max():.1e}, "
+        f"true residual max {true_res.max():.1e}, solution err max {err.max():.1e} (kappa {kappa:.1e}, bound {bound:.1e})")
+    assert res.status == 0
+    assert np.all(res.relres <= 1e-6)
+    assert err.max() <= bound
+    # inexact products (kappa * eps ~ 7e-3 FP32, ~0.1 BF16x3 here) delay the block Krylov process
+    # against the exact-arithmetic oracle; allow twice its count
+    assert res.iters <= 2 * o["iters"] + 5
+    assert true_res.max() <= 10 * (1e-6 + EPS_PRODUCT[prec]) * math.sqrt(kappa)
+    if r:
+        plain = gp.bcg(_gk(th), dev(X), dev(B.T), 400, 1e-6, precision=prec)
+        log(f"bcg {prec}: unpreconditioned {plain.iters} iterations, Nystrom r={r} {res.iters}")
+        assert o["iters"] < ab.altbbmm_solve(X, th, B, None, 1e-6, 400)["iters"]
+        assert res.iters < plain.iters
+
+
+def test_bcg_one_column_is_cg_on_the_gpu():
+    """s = 1: block CG is CG; it reaches the same solve as mBCG's first column."""
+    from paper_2109_09817_amd import gp
+    n = 900
+    X, y, th = _problem(n, seed=2)
+    r1 = gp.bcg(_gk(th), dev(X), dev(y[None, :]), 300, 1e-8, precision="fp32")
+    ref = np.linalg.solve(ok.khat(X, th), y)
+    e = np.linalg.norm(host(r1.W)[0] - ref) / np.linalg.norm(ref)
+    log(f"bcg s=1: iters {r1.iters}, err {e:.1e}")
+    assert r1.status == 0 and e <= 1e-4
+
+
+def test_bcg_reports_no_convergence():
+    from paper_2109_09817_amd import _lib, gp
+    n = 600
+    X, y, th = _problem(n, seed=3)
+    B = np.column_stack([y, np.random.default_rng(1).standard_normal((n, 3))])
+    res = gp.bcg(_gk(th), dev(X), dev(B.T), 2, 1e-12, precision="fp32")
+    assert res.status == _lib.GP_WNOCONV and res.iters == 2
