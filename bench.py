@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-altbbmm", action="store_true", help="skip the AltBBMM solve")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--profile-kmm", type=int, default=0, metavar="K",
@@ -246,6 +247,8 @@ def main():
 
     if not args.no_serve:
         extra["serving"] = serve_leg(args, gp, synth, torch, dev, np)
+    if not args.no_altbbmm:
+        extra["altbbmm"] = altbbmm_leg(gp, synth, torch, dev, np)
 
     out = {
         "metric": "K̂·V TFLOP/s + mBCG iters/s at N=1M (mixed vs FP32, rel err 1e-4); p99 predict latency",
@@ -333,6 +336,48 @@ def fit_c4(args, synth, torch, dev, np):
         "first_step_s": res.seconds[0], "mll": res.mll, "mbcg_iters": res.iters,
         "final": {"lengthscale_min": float(th[:d].min()), "lengthscale_max": float(th[:d].max()),
                   "outputscale": float(th[d]), "noise": float(th[d + 1])}}}), flush=True)
+
+
+def altbbmm_leg(gp, synth, torch, dev, np):
+    """AltBBMM solves (Sec. 3.2): block CG, s = 50 ([y | 49 N(0, 1) columns]), tolerance 1e-6 on every
+    column, with the symmetric Nystrom preconditioner of rank 512 over random landmark rows and without
+    it: the n = 131,072 and n = 917,504 models as configured (nearly diagonal kernels), and the
+    ill-conditioned variant (lengthscales x sqrt(2d)) at n = 16,384 with FP32 products."""
+    out = {"s": 50, "rank": 512, "tol": 1e-6}
+    cases = [("c3d", "c3d", None, False, "bf16x3"), ("c3o", "c3o", None, False, "bf16x3"),
+             ("c2_ill_conditioned_n16384", "c2", 16384, True, "fp32")]
+    for label, name, nsub, cond, prec in cases:
+        p = synth.make_problem(name, n=nsub, cond_variant=cond) if nsub else synth.make_problem(name)
+        n = p.X.shape[0]
+        X = torch.from_numpy(p.X).to(dev)
+        k = gp.Kernel(p.ell, p.sf, p.noise)
+        B = np.vstack([p.y[None, :], synth.random_block(n, 49, 11)])
+        Bd = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+        M = np.sort(np.random.default_rng(np.random.SeedSequence([p.cfg.seed, 12])).choice(n, 512, replace=False))
+        rec = {"n": n, "precision": prec}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = gp.nystrom_precond(k, X, M)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = gp.bcg(k, X, Bd, 200, 1e-6, pc=pc, precision=prec)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plain = gp.bcg(k, X, Bd, 200, 1e-6, pc=None, precision=prec)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        flops = res.iters * 2.0 * n * n * (p.X.shape[1] + 50)
+        rec["nystrom"] = {"precond_s": t1 - t0, "solve_s": t2 - t1, "iters": res.iters,
+                          "relres_max": float(res.relres.max()), "status": res.status,
+                          "products_tflops_nominal": flops / (t2 - t1) / 1e12}
+        rec["unpreconditioned"] = {"solve_s": t3 - t2, "iters": plain.iters, "relres_max": float(plain.relres.max()),
+                                   "status": plain.status}
+        log(f"altbbmm {label}: Nystrom precond {t1 - t0:.2f} s + solve {t2 - t1:.2f} s ({res.iters} it); "
+            f"unpreconditioned {t3 - t2:.2f} s ({plain.iters} it)")
+        out[label] = rec
+        del pc, res, plain, Bd, X
+        torch.cuda.empty_cache()
+    return out
 
 
 def serve_leg(args, gp, synth, torch, dev, np):

@@ -42,6 +42,9 @@ CASES = [
     (4096 + 17, 48, 16, True),  # several row blocks and a ragged tail
     (333, 7, 3, True),       # smaller than one workgroup
     (1000, 48, 33, True),    # three 16-column blocks
+    (1500, 48, 50, True),    # four column blocks, padded (the AltBBMM block size s = 50)
+    (700, 20, 64, True),     # four full column blocks
+    (600, 48, 100, True),    # two column groups of four blocks
     (1, 5, 1, True),         # degenerate: one point
 ]
 
