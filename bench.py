@@ -44,23 +44,48 @@ def log(msg):
 SWEEP_COUNTERS = os.path.join(ROOT, "profiles", "sweep_bf16x3_n917504_t16_counters.md")
 
 
+def _definition(text, name):
+    """Source text of the first definition of `name` (function or struct template) in `text`: from the
+    template/declaration line through its matching closing brace."""
+    import re
+    m = re.search(r"(?m)^(template <[^\n]*>\n)?[^\n]*\b" + re.escape(name) + r"\b[^;\n]*\{", text)
+    if not m:
+        return ""
+    depth, i = 0, text.index("{", m.start())
+    for j in range(i, len(text)):
+        depth += {"{": 1, "}": -1}.get(text[j], 0)
+        if depth == 0:
+            return text[m.start():j + 1]
+    return ""
+
+
+# The sweep kernel and everything it executes: its source text decides whether recorded counters apply.
+SWEEP_SOURCES = [("paper_2109_09817_amd/csrc/kmm.hip", ["profile", "NAOf", "ChunkUnits", "sweep_bf16x3_kernel"]),
+                 ("paper_2109_09817_amd/csrc/mfma_bf16.h", ["split_bf16x8", "vperm"])]
+
+
+def sweep_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for path, names in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, path)) as fh:
+            text = fh.read()
+        for name in names:
+            h.update(_definition(text, name).encode())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per n = 917,504 sweep launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, calibrated on a copy kernel), or None when the sweep's sources have changed since."""
-    import hashlib
+    WRITE_SIZE, calibrated on a copy kernel), or None when the sweep's source has changed since."""
     try:
         text = open(SWEEP_COUNTERS).read()
     except OSError:
         return None
-    vals = dict(l.split(" = ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "sources_sha256")))
-    if "sources_sha256" not in vals:
+    vals = dict(l.split(" = ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "sweep_source_sha256")))
+    if "sweep_source_sha256" not in vals:
         return None
-    digest, files = vals["sources_sha256"].split("  (", 1)
-    h = hashlib.sha256()
-    for f in files.rstrip(")").split(", "):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return float(vals["traffic_bytes_per_launch"]) if h.hexdigest() == digest.strip() else None
+    return float(vals["traffic_bytes_per_launch"]) if vals["sweep_source_sha256"].strip() == sweep_source_digest() else None
 
 
 def main():
