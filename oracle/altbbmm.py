@@ -33,12 +33,21 @@ import numpy as np
 from .kernel import Theta, kernel, khat
 
 
-def nystrom_matrix(X, th: Theta, landmarks) -> np.ndarray:
-    """Dense P = K_XM K_MM^{-1} K_MX + sigma^2 I for the landmark row indices M."""
+def nystrom_matrix(X, th: Theta, landmarks, rcond: float = 0.0) -> np.ndarray:
+    """Dense P = K_XM K_MM^{-1} K_MX + sigma^2 I for the landmark row indices M.  With rcond > 0 the
+    inverse is the pseudo-inverse over the eigenvalues of K_MM above rcond * lambda_max (nearly
+    repeated landmarks make K_MM numerically singular)."""
     M = np.asarray(landmarks, dtype=np.int64)
     KXM = kernel(X, X[M], th)
     KMM = KXM[M]
-    Q = KXM @ np.linalg.solve(KMM, KXM.T)
+    if rcond > 0.0:
+        lam, U = np.linalg.eigh(0.5 * (KMM + KMM.T))
+        keep = lam > rcond * lam.max()
+        C = U[:, keep] / np.sqrt(lam[keep])
+        F = KXM @ C
+        Q = F @ F.T
+    else:
+        Q = KXM @ np.linalg.solve(KMM, KXM.T)
     Q = 0.5 * (Q + Q.T)
     return Q + th.noise * np.eye(X.shape[0])
 
@@ -81,10 +90,10 @@ def block_cg(matmul, B: np.ndarray, tol: float, max_iter: int) -> dict:
     return {"X": X, "iters": iters, "relres": relres, "relres_hist": hist, "alphas": alphas, "betas": betas}
 
 
-def altbbmm_solve(X, th: Theta, B: np.ndarray, landmarks, tol: float, max_iter: int) -> dict:
+def altbbmm_solve(X, th: Theta, B: np.ndarray, landmarks, tol: float, max_iter: int, rcond: float = 0.0) -> dict:
     """Block CG on P^{-1/2} K_hat P^{-1/2} (P Nystrom over ``landmarks``, or the identity when None)."""
     Kh = khat(X, th)
-    S = np.eye(X.shape[0]) if landmarks is None else inv_sqrt(nystrom_matrix(X, th, landmarks))
+    S = np.eye(X.shape[0]) if landmarks is None else inv_sqrt(nystrom_matrix(X, th, landmarks, rcond))
     A = S @ Kh @ S
     res = block_cg(lambda D: A @ D, S @ B, tol, max_iter)
     res["W"] = S @ res["X"]

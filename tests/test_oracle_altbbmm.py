@@ -98,3 +98,20 @@ def test_altbbmm_solution_and_iteration_bound():
     np.testing.assert_allclose(pre["W"], ref, rtol=0, atol=1e-7 * np.abs(ref).max())
     assert pre["iters"] <= -(-(120 - r + 1) // s) + 2
     assert pre["iters"] < plain["iters"]
+
+
+def test_truncated_nystrom_keeps_the_bounds_and_matches_when_nothing_is_dropped():
+    """The pseudo-inverse form drops only directions of K_MM below rcond * lambda_max: it equals the
+    exact form on a well-conditioned K_MM, and with a nearly repeated landmark it stays a lower bound
+    of K (K - Q PSD), so the preconditioned spectrum stays >= 1."""
+    X, th, rng = _problem(seed=6)
+    M = rng.choice(X.shape[0], 20, replace=False)
+    np.testing.assert_allclose(ab.nystrom_matrix(X, th, M, 1e-7), ab.nystrom_matrix(X, th, M), rtol=0, atol=1e-9)
+    X2 = np.vstack([X, X[M[:3]] + 1e-7])  # three landmarks repeated to 1e-7
+    M2 = np.concatenate([M, X.shape[0] + np.arange(3)])
+    P = ab.nystrom_matrix(X2, th, M2, 1e-7)
+    Q = P - th.noise * np.eye(X2.shape[0])
+    K = ok.kernel(X2, X2, th)
+    assert np.linalg.eigvalsh(K - Q).min() >= -1e-9
+    S = ab.inv_sqrt(P)
+    assert np.linalg.eigvalsh(S @ ok.khat(X2, th) @ S).min() >= 1 - 1e-7
