@@ -60,6 +60,7 @@ extern "C" {
 /* ---- arithmetic of the kernel-matrix products ---- */
 #define GP_PREC_FP32 0   /* FP32 matrix-core operands and accumulation */
 #define GP_PREC_BF16X3 1 /* BF16 hi/lo split operands, three products, FP32 accumulation */
+#define GP_PREC_FP64 2   /* FP64 throughout (low-noise regime); gp_kmm, gp_mbcg and gp_bcg only, d <= 64 */
 
 #define GP_MAX_D 128 /* largest feature count d */
 
@@ -285,49 +286,57 @@ int gp_lanczos_quadrature(const double* alpha, const double* beta, int32_t J, in
  * Nystrom approximation over r landmark rows M,
  *   P = K_XM K_MM^{-1} K_MX + sigma^2 I,
  * in the factored form of its inverse square root
- *   P^{-1/2} = sigma^{-1} I + K_XM H K_MX.
+ *   P^{-1/2} = sigma^{-1} I + Z^T diag(g) Z,
+ * where Z^T = U_F S^{1/2} is the thin SVD factor of F = K_XM C, C C^T the
+ * inverse of K_MM, and g_m = -1 / (sigma q_m (sigma + q_m)), q_m = sqrt(S_m +
+ * sigma^2).  K_MM^{-1} is the pseudo-inverse over the eigenvalues of K_MM
+ * above 1e-7 of the largest (nearly repeated landmarks make K_MM numerically
+ * singular; the dropped directions are left to CG), so only the first k <= r
+ * rows of Z are used: rows k..r-1 and g[k..r-1] are zero.
  * landmarks: host, r distinct indices in [0, n) (the paper draws them at
- * random; pass the draw).  KXM: device, n x r column-major (ld = n), the
- * kernel columns K(X, X[M]) in FP64.  H: device, r x r (symmetric).
+ * random; pass the draw).  Z: device, r x n row-major (row m = factor column
+ * m; the sum of Z_m Z_m^T is the approximation K_XM K_MM^{-1} K_MX).  g:
+ * device, r.  Both FP64, owned by the caller.
  * Requires sigma^2 > 0 and 1 <= r <= min(n, 1024).  Errors: GP_EINVAL (sizes,
- * repeated or out-of-range landmarks), GP_ENOTPD (K_MM not positive definite),
- * GP_ENONFINITE, GP_EWORKSPACE, GP_EHIP.  Synchronous (the r x r factorisation
- * and eigendecomposition run on the host).
+ * repeated or out-of-range landmarks), GP_ENOTPD (K_MM numerically zero, or an
+ * eigendecomposition that does not converge), GP_ENONFINITE, GP_EWORKSPACE,
+ * GP_EHIP.  Synchronous (the two r x r eigendecompositions run on the host).
  * Workspace: gp_workspace_bytes(GP_OP_NYSTROM, n, 0, d, 0, r, any precision).
  */
 int gp_nystrom_precond(const gp_kernel* kern, const double* X, int64_t n,
-                       const int64_t* landmarks, int32_t r, double* KXM, double* H,
+                       const int64_t* landmarks, int32_t r, double* Z, double* g,
                        void* ws, size_t ws_bytes, void* stream);
 
 /*
- * gp_nystrom_apply - Y = P^{-1/2} V = sigma^{-1} V + KXM (H (KXM^T V)) for a
- * device n x s block V (column-major, ld = n), s <= 64; Y likewise (may equal
- * V).  KXM, H from gp_nystrom_precond; noise = its sigma^2.  Asynchronous.
+ * gp_nystrom_apply - Y = P^{-1/2} V = sigma^{-1} V + Z^T (diag(g) (Z V)) for
+ * a device n x s block V (column-major, ld = n), s <= 64; Y likewise (may
+ * equal V).  Z, g from gp_nystrom_precond; noise = its sigma^2.  Asynchronous.
  * Workspace: gp_workspace_bytes(GP_OP_NYSTROM_APPLY, n, 0, 1, s, r, any precision).
  */
-int gp_nystrom_apply(const double* KXM, const double* H, int64_t n, int32_t r, double noise,
+int gp_nystrom_apply(const double* Z, const double* g, int64_t n, int32_t r, double noise,
                      const double* V, int32_t s, double* Y,
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gp_bcg - AltBBMM solve (Sec. 3.1 block CG, Sec. 3.2): block conjugate
  * gradients on the symmetrically preconditioned system
- *   P^{-1/2} K_hat P^{-1/2} Z = P^{-1/2} B,   W = P^{-1/2} Z  (= K_hat^{-1} B),
+ *   P^{-1/2} K_hat P^{-1/2} U = P^{-1/2} B,   W = P^{-1/2} U  (= K_hat^{-1} B),
  * with P the Nystrom preconditioner of gp_nystrom_precond (r > 0) or the
- * identity (r = 0; KXM, H ignored).  Iteration (O'Leary): Q = A D,
- * alpha = (D^T Q)^{-1} R^T R, Z += D alpha, R -= Q alpha,
+ * identity (r = 0; Z, g ignored).  Iteration (O'Leary): Q = A D,
+ * alpha = (D^T Q)^{-1} R^T R, U += D alpha, R -= Q alpha,
  * beta = (R_old^T R_old)^{-1} R^T R, D = R + D beta.  Stops when every column's
  * relative residual ||R_c|| / ||P^{-1/2} B_c|| <= tol (the paper: 1e-6 for all
  * s = 50 columns); GP_WNOCONV after max_iter.  K_hat products in `precision`
  * (as gp_kmm); recurrences, preconditioner and the s x s solves in FP64.
  * B: device n x s (ldb >= n), nonzero columns, s <= 64.  W: device n x s
  * (ldw >= n).  iters: host, the iterations run.  relres: host, s final
- * relative residuals.  GP_ENOTPD on block breakdown (D^T A D or R^T R not
- * positive definite).  Synchronises twice per iteration.
+ * relative residuals.  The s x s systems are solved by pivoted LU on the host;
+ * GP_ENOTPD on block breakdown (a singular D^T A D or R^T R).  Synchronises
+ * twice per iteration.
  * Workspace: gp_workspace_bytes(GP_OP_BCG, n, 0, d, s, r, precision).
  */
 int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
-           const double* KXM, const double* H, int32_t r,
+           const double* Z, const double* g, int32_t r,
            const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
            double* W, int64_t ldw, int32_t* iters, double* relres,
            void* ws, size_t ws_bytes, void* stream);

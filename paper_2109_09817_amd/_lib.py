@@ -19,6 +19,7 @@ GP_MATERN52 = 0
 GP_RBF = 1
 GP_PREC_FP32 = 0
 GP_PREC_BF16X3 = 1
+GP_PREC_FP64 = 2
 GP_MAX_D = 128
 
 GP_OP_KMM = 1

@@ -1,24 +1,29 @@
 // AltBBMM (Sec. 3.2): block conjugate gradients (Sec. 3.1) in FP64 on the
-// symmetrically preconditioned system P^{-1/2} K_hat P^{-1/2} Z = P^{-1/2} B,
-// W = P^{-1/2} Z, with the Nystrom preconditioner over r landmark rows M
+// symmetrically preconditioned system P^{-1/2} K_hat P^{-1/2} U = P^{-1/2} B,
+// W = P^{-1/2} U, with the Nystrom preconditioner over r landmark rows M
 //
 //   P = K_XM K_MM^{-1} K_MX + sigma^2 I.
 //
-// Spectral square root.  With K_MM = L L^T, F = K_XM L^{-T} (so K_XM K_MM^{-1}
-// K_MX = F F^T) and the eigendecomposition F^T F = L^{-1} (K_MX K_XM) L^{-T} =
-// V diag(S) V^T, the thin SVD F = U S^{1/2} V^T gives P = U diag(S + sigma^2) U^T
-// + sigma^2 (I - U U^T), hence
+// Spectral square root.  K_MM^{-1} is taken rank-revealing: K_MM = U diag(lam) U^T
+// and C = U_k diag(lam_k)^{-1/2} over the eigenvalues above 1e-7 lam_max (nearly
+// repeated landmarks make K_MM numerically singular; the dropped directions are
+// left to CG).  F = K_XM C (n x k, formed on the GPU) carries the approximation
+// F F^T; with the eigendecomposition F^T F = V diag(S) V^T the thin SVD is
+// F = U_F S^{1/2} V^T, and P = U_F diag(S + sigma^2) U_F^T + sigma^2 (I - U_F U_F^T):
 //
-//   P^{-1/2} = sigma^{-1} I + K_XM H K_MX,
-//   H = L^{-T} V diag(g) V^T L^{-1},  g = ((S + sigma^2)^{-1/2} - sigma^{-1}) / S
+//   P^{-1/2} = sigma^{-1} I + Z^T diag(g) Z,   Z^T = F V = U_F S^{1/2},
+//   g = ((S + sigma^2)^{-1/2} - sigma^{-1}) / S
 //     = -1 / (sigma sqrt(S + sigma^2) (sigma + sqrt(S + sigma^2))).
 //
-// K_XM (n x r) is materialised once in FP64; H is formed on the host from the
-// r x r matrices K_MM and K_MX K_XM.  One application costs two tall-skinny
-// products with K_XM.  The block CG recurrences (O'Leary):
-//   Q = A D;  alpha = (D^T Q)^{-1} (R^T R);  X += D alpha;  R -= Q alpha;
+// The factor form matters at low noise: F^T F is taken from F itself, never as
+// C^T (K_MX K_XM) C, whose rounding (eps |K|^2 |C|^2 ~ eps |K|^2 / lam_min(K_MM))
+// can exceed sigma^2; and P^{-1/2} is applied through Z (rows of norm S^{1/2}),
+// never through K_XM and an r x r middle factor with entries ~ |C|^2 |g|.
+// One application costs two tall-skinny products with Z.  The block CG
+// recurrences (O'Leary):
+//   Q = A D;  alpha = (D^T Q)^{-1} (R^T R);  U += D alpha;  R -= Q alpha;
 //   beta = (R_old^T R_old)^{-1} (R^T R);  D = R + D beta,
-// with the s x s Gram matrices reduced on the GPU and factorised on the host.
+// with the s x s Gram matrices reduced on the GPU and solved on the host.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -32,6 +37,7 @@ constexpr int kNysTile = 32;   // landmarks per workgroup of the column kernel
 constexpr int kTallK = 32;     // K rows of C staged per step of the tall product
 constexpr int kTallMaxS = 64;  // columns of the tall product
 constexpr int kNysMaxR = 1024;
+constexpr double kNysRcond = 1e-7;  // K_MM eigenvalues kept: lam > kNysRcond * lam_max
 
 // KXM[j n + p] = s_f m(r(x_p, x_{M_j})) in FP64.  sc[f]: feature scale (Matern
 // sqrt5 / l_f, so that u = sqrt5 r; RBF 1 / l_f).
@@ -86,14 +92,14 @@ __global__ void gather_landmark_rows_kernel(const double* __restrict__ KXM, int6
   out[e] = KXM[j * n + M[i]];
 }
 
-// Y = alpha V + A C for A (nrows x kk, column-major, lda), C (kk x s, row-major),
-// V and Y (nrows x s): column-major with ldv / ldy, or (ROWMAJOR) row-major with
-// s per row.  One thread per row; each thread reads all of its row of A before
+// Y = alpha V + A C for A (nrows x kk, column-major, lda), C (kk x s, row-major
+// with row stride ldc), V and Y (nrows x s): column-major with ldv / ldy, or
+// (ROWMAJOR) row-major with s per row.  One thread per row; each thread reads all of its row of A before
 // writing its row of Y, so Y may alias A or V.
 template <bool ROWMAJOR>
 __global__ __launch_bounds__(256) void tall_product_kernel(const double* __restrict__ A, int64_t lda,
                                                            int64_t nrows, int kk, const double* __restrict__ C,
-                                                           int s, double alpha, const double* V, int64_t ldv,
+                                                           int64_t ldc, int s, double alpha, const double* V, int64_t ldv,
                                                            double* Y, int64_t ldy) {
   __shared__ double Cs[kTallK][kTallMaxS];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(256) void tall_product_kernel(const double* __restr
     __syncthreads();
     for (int e = threadIdx.x; e < kTallK * kTallMaxS; e += blockDim.x) {
       const int k = e / kTallMaxS, c = e - k * kTallMaxS;
-      Cs[k][c] = (k0 + k < kk && c < s) ? C[(int64_t)(k0 + k) * s + c] : 0.0;
+      Cs[k][c] = (k0 + k < kk && c < s) ? C[(int64_t)(k0 + k) * ldc + c] : 0.0;
     }
     __syncthreads();
     if (p < nrows) {
@@ -130,15 +136,35 @@ __global__ __launch_bounds__(256) void tall_product_kernel(const double* __restr
   }
 }
 
-static hipError_t tall_product(const double* A, int64_t lda, int64_t nrows, int kk, const double* C, int s,
-                               double alpha, const double* V, int64_t ldv, double* Y, int64_t ldy, bool rowmajor,
-                               hipStream_t st) {
+static hipError_t tall_product(const double* A, int64_t lda, int64_t nrows, int kk, const double* C, int64_t ldc,
+                               int s, double alpha, const double* V, int64_t ldv, double* Y, int64_t ldy,
+                               bool rowmajor, hipStream_t st) {
   const unsigned grid = (unsigned)((nrows + 255) / 256);
   if (rowmajor)
-    tall_product_kernel<true><<<grid, 256, 0, st>>>(A, lda, nrows, kk, C, s, alpha, V, ldv, Y, ldy);
+    tall_product_kernel<true><<<grid, 256, 0, st>>>(A, lda, nrows, kk, C, ldc, s, alpha, V, ldv, Y, ldy);
   else
-    tall_product_kernel<false><<<grid, 256, 0, st>>>(A, lda, nrows, kk, C, s, alpha, V, ldv, Y, ldy);
+    tall_product_kernel<false><<<grid, 256, 0, st>>>(A, lda, nrows, kk, C, ldc, s, alpha, V, ldv, Y, ldy);
   return hipGetLastError();
+}
+
+// Y = A C for C (kk x m row-major) with any m: column blocks of kTallMaxS.
+// A (nrows x kk) and Y (nrows x m) column-major with ld nrows.
+static hipError_t tall_product_wide(const double* A, int64_t nrows, int kk, const double* C, int m, double* Y,
+                                    hipStream_t st) {
+  for (int c0 = 0; c0 < m; c0 += kTallMaxS) {
+    const int sc = std::min(kTallMaxS, m - c0);
+    hipError_t e = tall_product(A, nrows, nrows, kk, C + c0, m, sc, 0.0, nullptr, 0, Y + (int64_t)c0 * nrows,
+                                nrows, false, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// out[e] = g[e / s] in[e] for e < r s (rows of an r x s row-major block).
+__global__ void scale_rows_kernel(const double* __restrict__ in, const double* __restrict__ g, int r, int s,
+                                  double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < r * s) out[e] = g[e / s] * in[e];
 }
 
 // A^T B with the row split sized to the output: ~2048 workgroups whatever pa, qb.
@@ -148,6 +174,12 @@ static int64_t gram_blocks(int64_t n, int pa, int qb) {
 }
 static size_t gram_partial_doubles(int64_t n, int pa, int qb) {
   return (size_t)gram_blocks(n, pa, qb) * pa * qb;
+}
+// Largest partial buffer of a k x k Gram over k <= r (the row split grows as k shrinks).
+static size_t gram_partial_doubles_upto(int64_t n, int r) {
+  size_t m = 0;
+  for (int k = 1; k <= r; ++k) m = std::max(m, gram_partial_doubles(n, k, k));
+  return m;
 }
 static hipError_t gram(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
                        hipStream_t st) {
@@ -160,106 +192,88 @@ size_t nystrom_ws_bytes(int d, int64_t n, int r) {
   size_t b = 0;
   b += align256((size_t)r * 8);                                // landmark indices
   b += align256((size_t)d * 8);                                // feature scales
-  b += 2 * align256((size_t)r * r * 8);                        // K_MM, K_MX K_XM
-  b += align256(gram_partial_doubles(n, r, r) * 8);            // Gram partials
+  b += 2 * align256((size_t)r * r * 8);                        // K_MM then F^T F; C then V
+  b += align256((size_t)n * r * 8);                            // F = K_XM C
+  b += align256(gram_partial_doubles_upto(n, r) * 8);          // Gram partials (F^T F, k <= r)
   return b + 4096;
 }
 
-// host: solve L Y = B (L lower, row-major k x k; B row-major k x m, overwritten)
-static void host_lower_solve(const std::vector<double>& L, int k, std::vector<double>& B, int m) {
-  for (int i = 0; i < k; ++i) {
-    double* bi = &B[(size_t)i * m];
-    for (int j = 0; j < i; ++j) {
-      const double l = L[(size_t)i * k + j];
-      const double* bj = &B[(size_t)j * m];
-      for (int c = 0; c < m; ++c) bi[c] -= l * bj[c];
-    }
-    const double inv = 1.0 / L[(size_t)i * k + i];
-    for (int c = 0; c < m; ++c) bi[c] *= inv;
-  }
-}
-// host: solve L^T Y = B
-static void host_upper_solve(const std::vector<double>& L, int k, std::vector<double>& B, int m) {
-  for (int i = k - 1; i >= 0; --i) {
-    double* bi = &B[(size_t)i * m];
-    for (int j = i + 1; j < k; ++j) {
-      const double l = L[(size_t)j * k + i];
-      const double* bj = &B[(size_t)j * m];
-      for (int c = 0; c < m; ++c) bi[c] -= l * bj[c];
-    }
-    const double inv = 1.0 / L[(size_t)i * k + i];
-    for (int c = 0; c < m; ++c) bi[c] *= inv;
-  }
-}
-static void host_transpose(std::vector<double>& A, int k) {
-  for (int i = 0; i < k; ++i)
-    for (int j = i + 1; j < k; ++j) std::swap(A[(size_t)i * k + j], A[(size_t)j * k + i]);
+// Symmetrise a row-major m x m matrix evaluated in two halves.
+static void symmetrise(std::vector<double>& A, int m) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) A[(size_t)i * m + j] = A[(size_t)j * m + i] = 0.5 * (A[(size_t)i * m + j] + A[(size_t)j * m + i]);
 }
 
-int run_nystrom(const gp_kernel* kern, const double* X, int64_t n, const int64_t* landmarks, int r, double* KXM,
-                double* H, void* ws, size_t ws_bytes, hipStream_t st) {
+int run_nystrom(const gp_kernel* kern, const double* X, int64_t n, const int64_t* landmarks, int r, double* Zt,
+                double* g, void* ws, size_t ws_bytes, hipStream_t st) {
   const int d = kern->d;
   Carve cv(ws, ws_bytes);
   int64_t* Mdev = cv.take<int64_t>(r);
   double* scd = cv.take<double>(d);
-  double* KMM = cv.take<double>((size_t)r * r);
-  double* G = cv.take<double>((size_t)r * r);
-  double* part = cv.take<double>(gram_partial_doubles(n, r, r));
+  double* Sq = cv.take<double>((size_t)r * r);   // K_MM, later F^T F
+  double* Cd = cv.take<double>((size_t)r * r);   // C, later V
+  double* F = cv.take<double>((size_t)n * r);
+  double* part = cv.take<double>(gram_partial_doubles_upto(n, r));
   if (!part) return fail(GP_EWORKSPACE, "gp_nystrom_precond: workspace layout failed");
   std::vector<double> sc(d);
   for (int f = 0; f < d; ++f)
     sc[f] = (kern->kind == GP_MATERN52 ? std::sqrt(5.0) : 1.0) / kern->lengthscale[f];
   GPK_HIP(hipMemcpyAsync(Mdev, landmarks, sizeof(int64_t) * r, hipMemcpyHostToDevice, st));
   GPK_HIP(hipMemcpyAsync(scd, sc.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
+  // K_XM (column j = K(X, x_{M_j})) into the output buffer; it is replaced by the factor below
+  double* KXM = Zt;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)((r + kNysTile - 1) / kNysTile));
   if (kern->kind == GP_MATERN52)
     kernel_cols_kernel<GP_MATERN52><<<grid, 256, 0, st>>>(X, n, d, scd, Mdev, r, kern->outputscale, KXM);
   else
     kernel_cols_kernel<GP_RBF><<<grid, 256, 0, st>>>(X, n, d, scd, Mdev, r, kern->outputscale, KXM);
   GPK_HIP(hipGetLastError());
-  gather_landmark_rows_kernel<<<(unsigned)(((int64_t)r * r + 255) / 256), 256, 0, st>>>(KXM, n, Mdev, r, KMM);
+  gather_landmark_rows_kernel<<<(unsigned)(((int64_t)r * r + 255) / 256), 256, 0, st>>>(KXM, n, Mdev, r, Sq);
   GPK_HIP(hipGetLastError());
-  GPK_HIP(gram(KXM, r, KXM, r, n, G, part, st));
-  std::vector<double> L((size_t)r * r), T((size_t)r * r);
-  GPK_HIP(hipMemcpyAsync(L.data(), KMM, sizeof(double) * r * r, hipMemcpyDeviceToHost, st));
-  GPK_HIP(hipMemcpyAsync(T.data(), G, sizeof(double) * r * r, hipMemcpyDeviceToHost, st));
+  std::vector<double> L((size_t)r * r);
+  GPK_HIP(hipMemcpyAsync(L.data(), Sq, sizeof(double) * r * r, hipMemcpyDeviceToHost, st));
   GPK_HIP(hipStreamSynchronize(st));
-  for (size_t e = 0; e < L.size(); ++e)
-    if (!std::isfinite(L[e]) || !std::isfinite(T[e])) return fail(GP_ENONFINITE, "gp_nystrom_precond: non-finite kernel");
+  for (double v : L)
+    if (!std::isfinite(v)) return fail(GP_ENONFINITE, "gp_nystrom_precond: non-finite kernel");
   // K_MM is stored column by column; it is symmetric up to the order of its evaluation
+  symmetrise(L, r);
+  // Rank-revealing inverse of K_MM: K_MM = U diag(lam) U^T, directions with lam <= kNysRcond lam_max
+  // (nearly repeated landmarks) dropped; C = U_keep diag(lam_keep)^{-1/2} (r x k).
+  std::vector<double> lam, U;
+  if (!sym_eig(r, L, lam, U)) return fail(GP_ENOTPD, "gp_nystrom_precond: eigen-decomposition of K_MM did not converge");
+  double lmax = 0.0;
+  for (double v : lam) lmax = std::max(lmax, v);
+  std::vector<int> keep;
   for (int i = 0; i < r; ++i)
-    for (int j = 0; j < i; ++j) L[(size_t)i * r + j] = L[(size_t)j * r + i] = 0.5 * (L[(size_t)i * r + j] + L[(size_t)j * r + i]);
-  if (!host_cholesky(L, r)) return fail(GP_ENOTPD, "gp_nystrom_precond: K_MM is not positive definite (repeated landmarks?)");
-  // T = L^{-1} G L^{-T}  (G symmetric: L^{-1} (L^{-1} G)^T)
-  host_lower_solve(L, r, T, r);
-  host_transpose(T, r);
-  host_lower_solve(L, r, T, r);
+    if (lam[i] > kNysRcond * lmax) keep.push_back(i);
+  const int k = (int)keep.size();
+  if (k == 0) return fail(GP_ENOTPD, "gp_nystrom_precond: K_MM is numerically zero");
+  std::vector<double> Cm((size_t)r * k);
   for (int i = 0; i < r; ++i)
-    for (int j = 0; j < i; ++j) T[(size_t)i * r + j] = T[(size_t)j * r + i] = 0.5 * (T[(size_t)i * r + j] + T[(size_t)j * r + i]);
+    for (int j = 0; j < k; ++j) Cm[(size_t)i * k + j] = U[(size_t)i * r + keep[j]] / std::sqrt(lam[keep[j]]);
+  // F = K_XM C (n x k, column-major) and F^T F (k x k)
+  GPK_HIP(hipMemcpyAsync(Cd, Cm.data(), sizeof(double) * r * k, hipMemcpyHostToDevice, st));
+  GPK_HIP(tall_product_wide(KXM, n, r, Cd, k, F, st));
+  GPK_HIP(gram(F, k, F, k, n, Sq, part, st));
+  std::vector<double> T((size_t)k * k);
+  GPK_HIP(hipMemcpyAsync(T.data(), Sq, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+  GPK_HIP(hipStreamSynchronize(st));  // also completes C's upload before Cm is released
+  for (double v : T)
+    if (!std::isfinite(v)) return fail(GP_ENONFINITE, "gp_nystrom_precond: non-finite F^T F");
+  symmetrise(T, k);
   std::vector<double> S, V;
-  if (!sym_eig(r, T, S, V)) return fail(GP_ENOTPD, "gp_nystrom_precond: eigen-decomposition did not converge");
+  if (!sym_eig(k, T, S, V)) return fail(GP_ENOTPD, "gp_nystrom_precond: eigen-decomposition of F^T F did not converge");
+  // Z^T = F V into the first k rows of the output (K_XM is no longer needed), zero rows beyond k
+  std::vector<double> gv(r, 0.0);
   const double sig = std::sqrt(kern->noise);
-  // K2 = V diag(g) V^T
-  std::vector<double> K2((size_t)r * r, 0.0), gv(r);
-  for (int m = 0; m < r; ++m) {
-    const double sm = std::max(S[m], 0.0);
-    const double q = std::sqrt(sm + kern->noise);
+  for (int m = 0; m < k; ++m) {
+    const double q = std::sqrt(std::max(S[m], 0.0) + kern->noise);
     gv[m] = -1.0 / (sig * q * (sig + q));
   }
-  for (int i = 0; i < r; ++i)
-    for (int m = 0; m < r; ++m) {
-      const double vg = V[(size_t)i * r + m] * gv[m];
-      double* row = &K2[(size_t)i * r];
-      const double* vrow = &V[0];
-      for (int j = 0; j < r; ++j) row[j] += vg * vrow[(size_t)j * r + m];
-    }
-  // H = L^{-T} K2 L^{-1}  (K2 symmetric: L^{-T} (L^{-T} K2)^T)
-  host_upper_solve(L, r, K2, r);
-  host_transpose(K2, r);
-  host_upper_solve(L, r, K2, r);
-  for (size_t e = 0; e < K2.size(); ++e)
-    if (!std::isfinite(K2[e])) return fail(GP_ENONFINITE, "gp_nystrom_precond: non-finite H");
-  GPK_HIP(hipMemcpyAsync(H, K2.data(), sizeof(double) * r * r, hipMemcpyHostToDevice, st));
+  GPK_HIP(hipMemcpyAsync(Cd, V.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+  GPK_HIP(tall_product_wide(F, n, k, Cd, k, Zt, st));
+  if (k < r) GPK_HIP(launch_fill(Zt + (int64_t)k * n, 0.0, (int64_t)(r - k) * n, st));
+  GPK_HIP(hipMemcpyAsync(g, gv.data(), sizeof(double) * r, hipMemcpyHostToDevice, st));
   GPK_HIP(hipStreamSynchronize(st));
   return GP_OK;
 }
@@ -270,15 +284,16 @@ size_t nystrom_apply_ws_bytes(int64_t n, int r, int s) {
   return 2 * align256((size_t)r * s * 8) + align256(gram_partial_doubles(n, std::max(r, 1), s) * 8) + 1024;
 }
 
-// Y = sigma^{-1} V + K_XM (H (K_XM^T V)); Y may alias V.
-static hipError_t nystrom_apply(const double* KXM, const double* H, int64_t n, int r, double noise, const double* V,
+// Y = sigma^{-1} V + Z^T (diag(g) (Z V)); Y may alias V.
+static hipError_t nystrom_apply(const double* Zt, const double* g, int64_t n, int r, double noise, const double* V,
                                 int64_t ldv, int s, double* Y, int64_t ldy, double* C1, double* C2, double* part,
                                 hipStream_t st) {
   hipError_t e;
   if (ldv != n) return hipErrorInvalidValue;  // gram() takes ld = n
-  if ((e = gram(KXM, r, V, s, n, C1, part, st)) != hipSuccess) return e;
-  if ((e = tall_product(H, r, r, r, C1, s, 0.0, nullptr, 0, C2, 0, true, st)) != hipSuccess) return e;
-  return tall_product(KXM, n, n, r, C2, s, 1.0 / std::sqrt(noise), V, ldv, Y, ldy, false, st);
+  if ((e = gram(Zt, r, V, s, n, C1, part, st)) != hipSuccess) return e;
+  scale_rows_kernel<<<(unsigned)((r * s + 255) / 256), 256, 0, st>>>(C1, g, r, s, C2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return tall_product(Zt, n, n, r, C2, s, s, 1.0 / std::sqrt(noise), V, ldv, Y, ldy, false, st);
 }
 
 // ---------------------------------------------------------------- block CG
@@ -292,20 +307,44 @@ size_t bcg_ws_bytes(int precision, int d, int64_t n, int r, int s) {
   return b + 4096;
 }
 
-// s x s: X = A^{-1} B with A symmetric positive definite (row-major); false on breakdown.
-static bool host_spd_solve(std::vector<double> A, int s, const std::vector<double>& B, std::vector<double>& X) {
-  for (int i = 0; i < s; ++i)
-    for (int j = 0; j < i; ++j) A[(size_t)i * s + j] = A[(size_t)j * s + i] = 0.5 * (A[(size_t)i * s + j] + A[(size_t)j * s + i]);
-  if (!host_cholesky(A, s)) return false;
+// s x s: X = A^{-1} B by LU with partial pivoting (row-major).  The block Gram
+// matrices are symmetric positive definite in exact arithmetic, but once the
+// search block is nearly rank-deficient rounding can make them indefinite, so
+// they are not factorised by Cholesky.  False when a pivot vanishes (breakdown).
+static bool host_lu_solve(std::vector<double> A, int s, const std::vector<double>& B, std::vector<double>& X) {
   X = B;
-  host_lower_solve(A, s, X, s);
-  host_upper_solve(A, s, X, s);
+  std::vector<int> perm(s);
+  for (int i = 0; i < s; ++i) perm[i] = i;
+  for (int k = 0; k < s; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < s; ++i)
+      if (std::fabs(A[(size_t)i * s + k]) > std::fabs(A[(size_t)piv * s + k])) piv = i;
+    const double pv = A[(size_t)piv * s + k];
+    if (!(pv != 0.0) || !std::isfinite(pv)) return false;
+    if (piv != k) {
+      for (int j = 0; j < s; ++j) std::swap(A[(size_t)k * s + j], A[(size_t)piv * s + j]);
+      for (int j = 0; j < s; ++j) std::swap(X[(size_t)k * s + j], X[(size_t)piv * s + j]);
+    }
+    for (int i = k + 1; i < s; ++i) {
+      const double f = A[(size_t)i * s + k] / pv;
+      if (f == 0.0) continue;
+      for (int j = k; j < s; ++j) A[(size_t)i * s + j] -= f * A[(size_t)k * s + j];
+      for (int j = 0; j < s; ++j) X[(size_t)i * s + j] -= f * X[(size_t)k * s + j];
+    }
+  }
+  for (int k = s - 1; k >= 0; --k) {
+    for (int j = 0; j < s; ++j) {
+      double v = X[(size_t)k * s + j];
+      for (int i = k + 1; i < s; ++i) v -= A[(size_t)k * s + i] * X[(size_t)i * s + j];
+      X[(size_t)k * s + j] = v / A[(size_t)k * s + k];
+    }
+  }
   for (double v : X)
     if (!std::isfinite(v)) return false;
   return true;
 }
 
-int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, const double* KXM, const double* H,
+int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, const double* Zt, const double* g,
             int r, const double* B, int64_t ldb, int s, int max_iter, double tol, double* W, int64_t ldw,
             int32_t* iters_out, double* relres, void* ws, size_t ws_bytes, hipStream_t st) {
   const int d = kern->d;
@@ -329,7 +368,7 @@ int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, co
   if (!Bd) return fail(GP_EWORKSPACE, "gp_bcg: workspace layout failed");
   const bool pre = r > 0;
   auto precond = [&](const double* in, double* out) -> hipError_t {
-    if (pre) return nystrom_apply(KXM, H, n, r, kern->noise, in, n, s, out, n, C1, C2, part, st);
+    if (pre) return nystrom_apply(Zt, g, n, r, kern->noise, in, n, s, out, n, C1, C2, part, st);
     return hipMemcpyAsync(out, in, sizeof(double) * ns, hipMemcpyDeviceToDevice, st);
   };
   auto gram_host = [&](const double* A, const double* Bm, std::vector<double>& out) -> hipError_t {
@@ -365,14 +404,14 @@ int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, co
     GPK_HIP(kmm_apply(plan, T1, n, s, T2, n, st, false));
     GPK_HIP(precond(T2, Q));
     GPK_HIP(gram_host(D, Q, DtQ));
-    if (!host_spd_solve(DtQ, s, RtR, alpha))
-      return fail(GP_ENOTPD, "gp_bcg: D^T A D not positive definite at iteration %d (block breakdown)", it);
+    if (!host_lu_solve(DtQ, s, RtR, alpha))
+      return fail(GP_ENOTPD, "gp_bcg: D^T A D singular at iteration %d (block breakdown)", it);
     nalpha = alpha;
     for (auto& v : nalpha) v = -v;
     GPK_HIP(hipMemcpyAsync(Ad, alpha.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
     GPK_HIP(hipMemcpyAsync(Bd, nalpha.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
-    GPK_HIP(tall_product(D, n, n, s, Ad, s, 1.0, Z, n, Z, n, false, st));   // Z += D alpha
-    GPK_HIP(tall_product(Q, n, n, s, Bd, s, 1.0, R, n, R, n, false, st));   // R -= Q alpha
+    GPK_HIP(tall_product(D, n, n, s, Ad, s, s, 1.0, Z, n, Z, n, false, st));   // Z += D alpha
+    GPK_HIP(tall_product(Q, n, n, s, Bd, s, s, 1.0, R, n, R, n, false, st));   // R -= Q alpha
     GPK_HIP(gram_host(R, R, RtRn));  // also orders the uploads above before alpha is rewritten
     ++it;
     bool all = true;
@@ -386,10 +425,10 @@ int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, co
       break;
     }
     if (it == max_iter) break;
-    if (!host_spd_solve(RtR, s, RtRn, beta))
+    if (!host_lu_solve(RtR, s, RtRn, beta))
       return fail(GP_ENOTPD, "gp_bcg: R^T R singular at iteration %d (block breakdown)", it);
     GPK_HIP(hipMemcpyAsync(Bd, beta.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
-    GPK_HIP(tall_product(D, n, n, s, Bd, s, 1.0, R, n, D, n, false, st));   // D = R + D beta
+    GPK_HIP(tall_product(D, n, n, s, Bd, s, s, 1.0, R, n, D, n, false, st));   // D = R + D beta
     RtR.swap(RtRn);
     GPK_HIP(hipStreamSynchronize(st));  // beta's upload completes before the host vector is reused
   }
@@ -417,20 +456,20 @@ static int check_landmarks(const int64_t* M, int r, int64_t n) {
 }
 
 extern "C" int gp_nystrom_precond(const gp_kernel* kern, const double* X, int64_t n, const int64_t* landmarks,
-                                  int32_t r, double* KXM, double* H, void* ws, size_t ws_bytes, void* stream) {
+                                  int32_t r, double* Z, double* g, void* ws, size_t ws_bytes, void* stream) {
   GPK_TRY(check_kernel(kern));
-  if (!X || !landmarks || !KXM || !H) return fail(GP_EINVAL, "gp_nystrom_precond: NULL argument");
+  if (!X || !landmarks || !Z || !g) return fail(GP_EINVAL, "gp_nystrom_precond: NULL argument");
   if (n < 1) return fail(GP_EINVAL, "gp_nystrom_precond: n must be >= 1");
   if (r < 1 || r > kNysMaxR || r > n) return fail(GP_EINVAL, "gp_nystrom_precond: r=%d outside [1, min(n, %d)]", r, kNysMaxR);
   if (!(kern->noise > 0.0)) return fail(GP_EINVAL, "gp_nystrom_precond: the noise must be > 0");
   GPK_TRY(check_landmarks(landmarks, r, n));
   GPK_TRY(check_ws(ws, ws_bytes, nystrom_ws_bytes(kern->d, n, r), "gp_nystrom_precond"));
-  return run_nystrom(kern, X, n, landmarks, r, KXM, H, ws, ws_bytes, (hipStream_t)stream);
+  return run_nystrom(kern, X, n, landmarks, r, Z, g, ws, ws_bytes, (hipStream_t)stream);
 }
 
-extern "C" int gp_nystrom_apply(const double* KXM, const double* H, int64_t n, int32_t r, double noise,
+extern "C" int gp_nystrom_apply(const double* Z, const double* g, int64_t n, int32_t r, double noise,
                                 const double* V, int32_t s, double* Y, void* ws, size_t ws_bytes, void* stream) {
-  if (!KXM || !H || !V || !Y) return fail(GP_EINVAL, "gp_nystrom_apply: NULL argument");
+  if (!Z || !g || !V || !Y) return fail(GP_EINVAL, "gp_nystrom_apply: NULL argument");
   if (n < 1 || r < 1 || r > kNysMaxR || r > n) return fail(GP_EINVAL, "gp_nystrom_apply: bad n or r");
   if (s < 1 || s > kTallMaxS) return fail(GP_EINVAL, "gp_nystrom_apply: s=%d outside [1, %d]", s, kTallMaxS);
   if (!(noise > 0.0) || !std::isfinite(noise)) return fail(GP_EINVAL, "gp_nystrom_apply: noise must be > 0");
@@ -440,15 +479,15 @@ extern "C" int gp_nystrom_apply(const double* KXM, const double* H, int64_t n, i
   double* C2 = cv.take<double>((size_t)r * s);
   double* part = cv.take<double>(gram_partial_doubles(n, r, s));
   if (!part) return fail(GP_EWORKSPACE, "gp_nystrom_apply: workspace layout failed");
-  GPK_HIP(nystrom_apply(KXM, H, n, r, noise, V, n, s, Y, n, C1, C2, part, (hipStream_t)stream));
+  GPK_HIP(nystrom_apply(Z, g, n, r, noise, V, n, s, Y, n, C1, C2, part, (hipStream_t)stream));
   return GP_OK;
 }
 
-extern "C" int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* KXM,
-                      const double* H, int32_t r, const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
+extern "C" int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z,
+                      const double* g, int32_t r, const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
                       double* W, int64_t ldw, int32_t* iters, double* relres, void* ws, size_t ws_bytes, void* stream) {
   GPK_TRY(check_kernel(kern));
-  GPK_TRY(check_precision(precision));
+  GPK_TRY(check_product_precision(precision));
   if (!X || !B || !W || !iters || !relres) return fail(GP_EINVAL, "gp_bcg: NULL argument");
   if (n < 1) return fail(GP_EINVAL, "gp_bcg: n must be >= 1");
   if (s < 1 || s > kTallMaxS) return fail(GP_EINVAL, "gp_bcg: s=%d outside [1, %d]", s, kTallMaxS);
@@ -456,9 +495,9 @@ extern "C" int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X,
   if (max_iter < 1) return fail(GP_EINVAL, "gp_bcg: max_iter must be >= 1");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(GP_EINVAL, "gp_bcg: tol must be finite and >= 0");
   if (r < 0 || r > kNysMaxR || r > n) return fail(GP_EINVAL, "gp_bcg: r=%d outside [0, min(n, %d)]", r, kNysMaxR);
-  if (r > 0 && (!KXM || !H)) return fail(GP_EINVAL, "gp_bcg: r > 0 needs KXM and H");
+  if (r > 0 && (!Z || !g)) return fail(GP_EINVAL, "gp_bcg: r > 0 needs Z and g");
   if (r > 0 && !(kern->noise > 0.0)) return fail(GP_EINVAL, "gp_bcg: the preconditioner needs noise > 0");
   GPK_TRY(check_ws(ws, ws_bytes, bcg_ws_bytes(precision, kern->d, n, r, s), "gp_bcg"));
-  return run_bcg(kern, precision, X, n, KXM, H, r, B, ldb, s, max_iter, tol, W, ldw, iters, relres, ws, ws_bytes,
+  return run_bcg(kern, precision, X, n, Z, g, r, B, ldb, s, max_iter, tol, W, ldw, iters, relres, ws, ws_bytes,
                  (hipStream_t)stream);
 }

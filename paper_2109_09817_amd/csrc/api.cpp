@@ -40,8 +40,14 @@ int check_kernel(const gp_kernel* k) {
 }
 
 int check_precision(int32_t p) {
+  if (p == GP_PREC_FP64) return fail(GP_EINVAL, "GP_PREC_FP64 is available for gp_kmm, gp_mbcg and gp_bcg only");
   if (p != GP_PREC_FP32 && p != GP_PREC_BF16X3) return fail(GP_EINVAL, "unknown precision %d", p);
   return GP_OK;
+}
+
+int check_product_precision(int32_t p) {
+  if (p == GP_PREC_FP64) return GP_OK;
+  return check_precision(p);
 }
 
 int check_ws(const void* ws, size_t have, size_t need, const char* op) {
@@ -64,7 +70,7 @@ extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X,
                       int64_t m, const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws,
                       size_t ws_bytes, void* stream) {
   GPK_TRY(check_kernel(kern));
-  GPK_TRY(check_precision(precision));
+  GPK_TRY(check_product_precision(precision));
   if (!X) return fail(GP_EINVAL, "gp_kmm: X is NULL");
   if (n < 1) return fail(GP_EINVAL, "gp_kmm: n=%lld must be >= 1", (long long)n);
   if (Z && m < 1) return fail(GP_EINVAL, "gp_kmm: m=%lld must be >= 1 when Z is given", (long long)m);

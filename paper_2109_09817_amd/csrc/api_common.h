@@ -31,6 +31,8 @@ int hip_fail(hipError_t e, const char* what, int line);
 
 int check_kernel(const gp_kernel* k);
 int check_precision(int32_t p);
+// Also accepts GP_PREC_FP64 (the entry points whose only tile product is K_hat V).
+int check_product_precision(int32_t p);
 int check_ws(const void* ws, size_t have, size_t need, const char* op);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -48,6 +48,12 @@ struct KmmPlan {
   void* vf = nullptr;
   double* part = nullptr;
   int64_t part_splits = 0;  // splits the partial buffer can hold
+  // FP64 form: the points themselves (caller memory), prescaled features and norms
+  const double* x64 = nullptr;  // b stream (training points), n x d
+  const double* z64 = nullptr;  // output rows, m x d
+  double* sc64 = nullptr;       // d feature scales
+  double* nb64 = nullptr;       // n squared norms of the scaled b points
+  double* na64 = nullptr;       // m squared norms of the scaled output rows
 };
 
 // Number of 32-wide K steps (BF16X3) or 16-wide groups (FP32) for d features.

@@ -40,6 +40,9 @@
 namespace gpk {
 
 constexpr int kFlush = 32;  // 32-point chunks accumulated in FP32 before the FP64 flush
+constexpr int kF64MaxD = 64;   // FP64 form: features held in registers
+constexpr int kF64Chunk = 32;  // FP64 form: points per LDS chunk
+constexpr int kF64Cols = 16;   // FP64 form: V columns per workgroup
 
 // The profile m(r) from S = r^2 scaled as above.  ACCURATE replaces the raw
 // v_sqrt_f32 by v_rsq_f32 plus one Newton step on the residual S - u^2; the raw
@@ -593,6 +596,7 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int kmm_ksteps(int precision, int d) {
+  if (precision == GP_PREC_FP64) return d <= kF64MaxD ? 1 : -1;
   if (precision == GP_PREC_BF16X3) {
     const int need = (3 * d + 6 + 31) / 32;
     static const int kAvail[] = {2, 4, 5, 7, 10, 13};
@@ -646,6 +650,8 @@ static size_t part_bytes_max(int64_t npad, int64_t mpad, int ntb, bool row_indep
 size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, int tmax) {
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
+  if (precision == GP_PREC_FP64)
+    return align256((size_t)d * 8) + align256((size_t)n * 8) + (square ? 0 : align256((size_t)m * 8)) + 256;
   const int64_t npad = round_up(n, 32);
   const int64_t mrows = square ? n : m;
   const int64_t mpad = round_up(mrows, 256);
@@ -681,6 +687,13 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
   p.ntb = (tmax + 15) / 16;
   p.sf = kern->outputscale;
   p.noise = kern->noise;
+  if (precision == GP_PREC_FP64) {
+    char* c = (char*)ws;
+    p.sc64 = (double*)c;  c += align256((size_t)p.d * 8);
+    p.nb64 = (double*)c;  c += align256((size_t)n * 8);
+    p.na64 = square ? p.nb64 : (double*)c;
+    return true;
+  }
   const int64_t bpad = std::max(p.npad, p.mpad);
   char* c = (char*)ws;
   p.xr = c;  c += align256((size_t)bpad * p.ks * 64);
@@ -696,6 +709,7 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
 
 // Model buffer: [b-stream fragments | b norms (FP32) | V fragments | FP64 norm scratch of the prepare step].
 size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax) {
+  if (precision == GP_PREC_FP64) return 0;  // prediction models use the matrix-core forms
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
   const int64_t npad = round_up(n, 32);
@@ -705,6 +719,7 @@ size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax) {
 
 // Query workspace: [row fragments | row norms (FP32) | FP64 norm scratch | partials].
 size_t kmm_query_bytes(int precision, int d, int64_t n, int64_t m, int tmax) {
+  if (precision == GP_PREC_FP64) return 0;
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
   const int64_t npad = round_up(n, 32);
@@ -752,6 +767,144 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
   return true;
 }
 
+// ------------------------------------------------------------------ FP64 form
+//
+// The low-noise regime (sigma^2 down to 1e-8, Sec. 3.2 and Sec. 4) needs K_hat V
+// to FP64 accuracy.  MI355X's FP64 matrix-core peak equals its FP64 vector peak,
+// so this form runs on the VALU: each thread owns one output row (its scaled
+// features in registers); 32-point chunks of the b stream and of V are staged in
+// LDS; r^2 = n_a + n_b - 2 x_a.x_b and the profile are evaluated in FP64; each
+// row sums sequentially over b (deterministic).  The diagonal entry is exactly
+// s_f (m(0) = 1) and sigma^2 V is added exactly.
+
+// sc64[f] = feature scale (thread f < d); nrm[p] = |x_p (.) sc|^2 for p < rows.
+__global__ void prep_fp64_kernel(const double* __restrict__ X, int64_t rows, int d, Scale sc,
+                                 double* __restrict__ sc64, double* __restrict__ nrm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc64 && p < d) sc64[p] = sc.s[p];
+  if (p >= rows) return;
+  double s = 0.0;
+  for (int f = 0; f < d; ++f) {
+    const double v = X[p * d + f] * sc.s[f];
+    s = fma(v, v, s);
+  }
+  nrm[p] = s;
+}
+
+template <int DP, int KIND>
+__global__ __launch_bounds__(256) void sweep_fp64_kernel(const double* __restrict__ Xb, const double* __restrict__ nb,
+                                                         int64_t n, const double* __restrict__ Xa,
+                                                         const double* __restrict__ na, int64_t m, int d,
+                                                         const double* __restrict__ sc64, const double* __restrict__ V,
+                                                         int64_t ldv, int t, double sf, double noise, int square,
+                                                         double* __restrict__ out, int64_t ldo) {
+  __shared__ double Bs[kF64Chunk][DP];
+  __shared__ double Ns[kF64Chunk];
+  __shared__ double Vs[kF64Cols][kF64Chunk];
+  __shared__ double Ss[DP];
+  const int tid = threadIdx.x;
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int c0 = blockIdx.y * kF64Cols;
+  for (int f = tid; f < DP; f += blockDim.x) Ss[f] = f < d ? sc64[f] : 0.0;
+  __syncthreads();
+  const bool live = a < m;
+  double xa[DP];
+#pragma unroll
+  for (int f = 0; f < DP; ++f) xa[f] = (live && f < d) ? Xa[a * d + f] * Ss[f] : 0.0;
+  const double naa = live ? na[a] : 0.0;
+  double acc[kF64Cols];
+#pragma unroll
+  for (int c = 0; c < kF64Cols; ++c) acc[c] = 0.0;
+  for (int64_t b0 = 0; b0 < n; b0 += kF64Chunk) {
+    __syncthreads();
+    for (int e = tid; e < kF64Chunk * DP; e += blockDim.x) {
+      const int j = e / DP, f = e - j * DP;
+      const int64_t b = b0 + j;
+      Bs[j][f] = (b < n && f < d) ? Xb[b * d + f] * Ss[f] : 0.0;
+    }
+    for (int e = tid; e < kF64Chunk; e += blockDim.x) Ns[e] = b0 + e < n ? nb[b0 + e] : 0.0;
+    for (int e = tid; e < kF64Chunk * kF64Cols; e += blockDim.x) {
+      const int c = e / kF64Chunk, j = e - c * kF64Chunk;
+      const int64_t b = b0 + j;
+      Vs[c][j] = (b < n && c0 + c < t) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
+    }
+    __syncthreads();
+    const int jn = n - b0 < kF64Chunk ? (int)(n - b0) : kF64Chunk;
+    // two points per step, each dot product as four interleaved partial sums:
+    // eight independent FMA chains instead of one chain of DP
+    for (int j = 0; j < jn; j += 2) {
+      double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int f = 0; f < DP; ++f) {
+        p0[f & 3] = fma(xa[f], Bs[j][f], p0[f & 3]);
+        p1[f & 3] = fma(xa[f], Bs[j + 1][f], p1[f & 3]);  // row j + 1 < kF64Chunk exists (zeros past n)
+      }
+      double mv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double* pp = q == 0 ? p0 : p1;
+        const double dot = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+        const double S = fmax(naa + Ns[j + q] - 2.0 * dot, 0.0);
+        if (j + q >= jn) {
+          mv[q] = 0.0;
+        } else if (square && b0 + j + q == a) {
+          mv[q] = 1.0;
+        } else if constexpr (KIND == GP_MATERN52) {
+          const double u = sqrt(S);
+          mv[q] = fma(u, fma(u, 1.0 / 3.0, 1.0), 1.0) * exp(-u);
+        } else {
+          mv[q] = exp(-0.5 * S);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kF64Cols; ++c) acc[c] = fma(mv[1], Vs[c][j + 1], fma(mv[0], Vs[c][j], acc[c]));
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int c = 0; c < kF64Cols; ++c) {
+    if (c0 + c < t) {
+      double y = sf * acc[c];
+      if (square) y = fma(noise, V[(int64_t)(c0 + c) * ldv + a], y);
+      out[(int64_t)(c0 + c) * ldo + a] = y;
+    }
+  }
+}
+
+// Feature scales of the FP64 form: Matern sqrt5 / l (so that r^2 -> u^2, u = sqrt5 r), RBF 1 / l.
+static Scale make_scale64(const gp_kernel* kern) {
+  Scale s{};
+  const double c = kern->kind == GP_MATERN52 ? std::sqrt(5.0) : 1.0;
+  for (int j = 0; j < kern->d; ++j) s.s[j] = c / kern->lengthscale[j];
+  return s;
+}
+
+template <int DP>
+static void launch_fp64(int kind, dim3 grid, const KmmPlan& p, const double* V, int64_t ldv, int t, double* out,
+                        int64_t ldo, hipStream_t st) {
+  if (kind == GP_MATERN52)
+    sweep_fp64_kernel<DP, GP_MATERN52><<<grid, 256, 0, st>>>(p.x64, p.nb64, p.n, p.z64, p.na64, p.m, p.d, p.sc64, V,
+                                                             ldv, t, p.sf, p.noise, p.square ? 1 : 0, out, ldo);
+  else
+    sweep_fp64_kernel<DP, GP_RBF><<<grid, 256, 0, st>>>(p.x64, p.nb64, p.n, p.z64, p.na64, p.m, p.d, p.sc64, V, ldv,
+                                                        t, p.sf, p.noise, p.square ? 1 : 0, out, ldo);
+}
+
+static hipError_t sweep_fp64(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
+                             hipStream_t st) {
+  if (!p.x64 || !p.z64 || !V || !out || t < 1) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((p.m + 255) / 256), (unsigned)((t + kF64Cols - 1) / kF64Cols));
+  const int dp = (p.d + 15) / 16 * 16;
+  switch (dp) {
+    case 16: launch_fp64<16>(p.kind, grid, p, V, ldv, t, out, ldo, st); break;
+    case 32: launch_fp64<32>(p.kind, grid, p, V, ldv, t, out, ldo, st); break;
+    case 48: launch_fp64<48>(p.kind, grid, p, V, ldv, t, out, ldo, st); break;
+    case 64: launch_fp64<64>(p.kind, grid, p, V, ldv, t, out, ldo, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 static Scale make_scale(const gp_kernel* kern) {
   Scale s{};
   const double c = kern->kind == GP_MATERN52 ? std::sqrt(5.0) * M_LOG2E : std::sqrt(0.5 * M_LOG2E);
@@ -781,6 +934,18 @@ static hipError_t prep_points(const KmmPlan& p, const Scale& sc, const double* P
 
 hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const double* Z,
                        hipStream_t st) {
+  if (p.precision == GP_PREC_FP64) {
+    if (!X || (!p.square && !Z) || !p.sc64) return hipErrorInvalidValue;
+    const Scale s64 = make_scale64(kern);
+    p.x64 = X;
+    p.z64 = p.square ? X : Z;
+    const int thr = 256;
+    prep_fp64_kernel<<<(unsigned)((std::max<int64_t>(p.n, p.d) + thr - 1) / thr), thr, 0, st>>>(X, p.n, p.d, s64,
+                                                                                              p.sc64, p.nb64);
+    if (!p.square)
+      prep_fp64_kernel<<<(unsigned)((p.m + thr - 1) / thr), thr, 0, st>>>(Z, p.m, p.d, s64, nullptr, p.na64);
+    return hipGetLastError();
+  }
   const Scale sc = make_scale(kern);
   if (p.square) {
     // one pass gives both sides; rows up to max(npad, mpad) so xc covers mpad
@@ -793,10 +958,12 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
 }
 
 hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, hipStream_t st) {
+  if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
   return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, st);
 }
 
 hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st) {
+  if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
   return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
 }
 
@@ -930,6 +1097,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
 
 hipError_t kmm_apply(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
                      hipStream_t st, bool row_independent) {
+  if (p.precision == GP_PREC_FP64) return sweep_fp64(p, V, ldv, t, out, ldo, st);
   hipError_t e = kmm_prepare_v(p, V, ldv, t, row_independent, st);
   if (e != hipSuccess) return e;
   return kmm_sweep(p, t, V, ldv, out, ldo, st, row_independent);

@@ -175,7 +175,8 @@ extern "C" int gp_lanczos_cache(const gp_kernel* kern, int32_t precision, const 
 extern "C" size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d, int32_t t, int32_t k,
                                      int32_t precision) {
   if (n < 1 || d < 1 || d > GP_MAX_D) return 0;
-  if (precision != GP_PREC_FP32 && precision != GP_PREC_BF16X3) return 0;
+  if (precision != GP_PREC_FP32 && precision != GP_PREC_BF16X3 && precision != GP_PREC_FP64) return 0;
+  if (precision == GP_PREC_FP64 && op != GP_OP_KMM && op != GP_OP_MBCG && op != GP_OP_BCG) return 0;
   switch (op) {
     case GP_OP_KMM:
       if (t < 1) return 0;

@@ -212,9 +212,10 @@ int run_mbcg(const gp_kernel* kern, int precision, const double* X, int64_t n, c
   return (flags.num_active > 0 && tol > 0.0) ? GP_WNOCONV : GP_OK;
 }
 
-static int check_common(const gp_kernel* kern, int precision, const double* X, int64_t n, const char* op) {
+static int check_common(const gp_kernel* kern, int precision, const double* X, int64_t n, const char* op,
+                        bool fp64_ok = false) {
   GPK_TRY(check_kernel(kern));
-  GPK_TRY(check_precision(precision));
+  GPK_TRY(fp64_ok ? check_product_precision(precision) : check_precision(precision));
   if (!X) return fail(GP_EINVAL, "%s: X is NULL", op);
   if (n < 1) return fail(GP_EINVAL, "%s: n=%lld must be >= 1", op, (long long)n);
   return GP_OK;
@@ -251,7 +252,7 @@ extern "C" int gp_probe_block(const double* y, int64_t n, int32_t t, const doubl
 extern "C" int gp_mbcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const gp_precond* pc,
                        const double* B, int32_t s, int32_t max_iter, double tol, double* U, double* Z0,
                        gp_mbcg_out* out, void* ws, size_t ws_bytes, void* stream) {
-  GPK_TRY(check_common(kern, precision, X, n, "gp_mbcg"));
+  GPK_TRY(check_common(kern, precision, X, n, "gp_mbcg", /*fp64_ok=*/true));
   if (!B || !U) return fail(GP_EINVAL, "gp_mbcg: B or U is NULL");
   if (s < 1 || s > kMaxBlock) return fail(GP_EINVAL, "gp_mbcg: s=%d outside [1, %d]", s, kMaxBlock);
   if (max_iter < 1) return fail(GP_EINVAL, "gp_mbcg: max_iter=%d must be >= 1", max_iter);

@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 
-PRECISION = {"fp32": _lib.GP_PREC_FP32, "bf16x3": _lib.GP_PREC_BF16X3}
+PRECISION = {"fp32": _lib.GP_PREC_FP32, "bf16x3": _lib.GP_PREC_BF16X3, "fp64": _lib.GP_PREC_FP64}
 KINDS = {"matern52": _lib.GP_MATERN52, "rbf": _lib.GP_RBF}
 
 
@@ -226,16 +226,22 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, probes: int, ra
 
 @dataclasses.dataclass
 class Nystrom:
-    """AltBBMM preconditioner: P^{-1/2} = sigma^{-1} I + K_XM H K_MX over landmark rows."""
+    """AltBBMM preconditioner over r landmark rows: P^{-1/2} = sigma^{-1} I + Z^T diag(g) Z."""
 
-    KXM: torch.Tensor       # (r, n): row j = kernel column K(X, x_{M_j})
-    H: torch.Tensor         # (r, r)
+    Z: torch.Tensor         # (r, n): rows beyond the kept rank are zero; sum_m Z_m Z_m^T = K_XM K_MM^+ K_MX
+    g: torch.Tensor         # (r,): zero beyond the kept rank
     landmarks: np.ndarray
     noise: float
 
     @property
     def rank(self) -> int:
-        return self.KXM.shape[0]
+        """Landmarks r (the size of Z and g)."""
+        return self.Z.shape[0]
+
+    @property
+    def kept(self) -> int:
+        """Directions of K_MM kept by its eigenvalue cut."""
+        return int(torch.count_nonzero(self.g).item())
 
 
 def nystrom_precond(kern: Kernel, X: torch.Tensor, landmarks) -> Nystrom:
@@ -244,26 +250,26 @@ def nystrom_precond(kern: Kernel, X: torch.Tensor, landmarks) -> Nystrom:
     _need(X, "X", (n, kern.d))
     M = np.ascontiguousarray(np.asarray(landmarks, dtype=np.int64))
     r = M.shape[0]
-    KXM = torch.empty((r, n), dtype=torch.float64, device=X.device)
-    H = torch.empty((r, r), dtype=torch.float64, device=X.device)
+    Z = torch.empty((r, n), dtype=torch.float64, device=X.device)
+    g = torch.empty((r,), dtype=torch.float64, device=X.device)
     ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM, n, 0, kern.d, 0, r, _lib.GP_PREC_FP32), X.device)
     ks, _keep = kern.struct()
     _lib.check(lib.gp_nystrom_precond(C.byref(ks), X.data_ptr(), n, M.ctypes.data_as(C.POINTER(C.c_int64)), r,
-                                      KXM.data_ptr(), H.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
-    return Nystrom(KXM, H, M, kern.noise)
+                                      Z.data_ptr(), g.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return Nystrom(Z, g, M, kern.noise)
 
 
 def nystrom_apply(pc: Nystrom, V: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """P^{-1/2} V for a (s, n) block."""
     lib = _lib.load()
-    r, n = pc.KXM.shape
+    r, n = pc.Z.shape
     s = V.shape[0]
     _need(V, "V", (s, n))
     if out is None:
         out = torch.empty_like(V)
     _need(out, "out", (s, n))
     ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM_APPLY, n, 0, 1, s, r, _lib.GP_PREC_FP32), V.device)
-    _lib.check(lib.gp_nystrom_apply(pc.KXM.data_ptr(), pc.H.data_ptr(), n, r, pc.noise, V.data_ptr(), s,
+    _lib.check(lib.gp_nystrom_apply(pc.Z.data_ptr(), pc.g.data_ptr(), n, r, pc.noise, V.data_ptr(), s,
                                     out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(V.device)))
     return out
 
@@ -291,8 +297,8 @@ def bcg(kern: Kernel, X: torch.Tensor, B: torch.Tensor, max_iter: int, tol: floa
     it = C.c_int32(0)
     rr = np.zeros(s)
     ks, _keep = kern.struct()
-    rc = _lib.check(lib.gp_bcg(C.byref(ks), p, X.data_ptr(), n, _ptr(None if pc is None else pc.KXM),
-                               _ptr(None if pc is None else pc.H), r, B.data_ptr(), n, s, max_iter, tol,
+    rc = _lib.check(lib.gp_bcg(C.byref(ks), p, X.data_ptr(), n, _ptr(None if pc is None else pc.Z),
+                               _ptr(None if pc is None else pc.g), r, B.data_ptr(), n, s, max_iter, tol,
                                W.data_ptr(), n, C.byref(it), rr.ctypes.data_as(C.POINTER(C.c_double)),
                                ws.data_ptr(), ws.numel(), _stream(X.device)))
     return BcgResult(W, int(it.value), rr, rc)

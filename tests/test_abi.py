@@ -123,20 +123,38 @@ def test_altbbmm_entry_points_validate_on_the_host(lib):
     it = C.c_int32(0)
     rr = np.zeros(64)
     rrp = rr.ctypes.data_as(C.POINTER(C.c_double))
-    base = dict(prec=1, n=10, kxm=None, h=None, r=0, ldb=10, s=2, mi=5, tol=1e-6, ldw=10)
+    base = dict(prec=1, n=10, z=None, g=None, r=0, ldb=10, s=2, mi=5, tol=1e-6, ldw=10)
 
     def call(**kw):
         a = dict(base)
         a.update(kw)
-        return lib.gp_bcg(C.byref(k), a["prec"], fake, a["n"], a["kxm"], a["h"], a["r"], fake, a["ldb"], a["s"],
+        return lib.gp_bcg(C.byref(k), a["prec"], fake, a["n"], a["z"], a["g"], a["r"], fake, a["ldb"], a["s"],
                           a["mi"], a["tol"], fake, a["ldw"], C.byref(it), rrp, None, 0, None)
 
     assert call(s=0) == _lib.GP_EINVAL and call(s=65) == _lib.GP_EINVAL
     assert call(ldb=9) == _lib.GP_EINVAL and call(ldw=9) == _lib.GP_EINVAL
     assert call(mi=0) == _lib.GP_EINVAL and call(tol=-1.0) == _lib.GP_EINVAL
-    assert call(r=3) == _lib.GP_EINVAL  # r > 0 without KXM, H
+    assert call(r=3) == _lib.GP_EINVAL  # r > 0 without Z, g
     assert call(prec=5) == _lib.GP_EINVAL
     assert call() == _lib.GP_EWORKSPACE
     assert lib.gp_workspace_bytes(_lib.GP_OP_BCG, 917504, 0, 48, 50, 512, 1) > 0
     assert lib.gp_workspace_bytes(_lib.GP_OP_BCG, 1000, 0, 48, 65, 0, 1) == 0
     assert lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM, 1000, 0, 48, 0, 1025, 1) == 0
+
+
+def test_fp64_products_are_limited_to_the_solves(lib):
+    from paper_2109_09817_amd import _lib
+    k, keep = _kernel()
+    fake = 4096
+    g = np.zeros(6)
+    w = np.ones(2)
+    rc = lib.gp_kmm_grad(C.byref(k), _lib.GP_PREC_FP64, fake, 10, fake, 10, fake, 10, 2,
+                         w.ctypes.data_as(C.POINTER(C.c_double)), g.ctypes.data_as(C.POINTER(C.c_double)),
+                         None, 0, None)
+    assert rc == _lib.GP_EINVAL and b"FP64" in lib.gp_last_error()
+    assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, 1000, 0, 48, 16, 0, _lib.GP_PREC_FP64) > 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_MBCG, 1000, 0, 48, 16, 0, _lib.GP_PREC_FP64) > 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_KMM_GRAD, 1000, 0, 48, 16, 0, _lib.GP_PREC_FP64) == 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_MLL, 1000, 0, 48, 16, 10, _lib.GP_PREC_FP64) == 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, 1000, 0, 65, 16, 0, _lib.GP_PREC_FP64) == 0  # d <= 64
+    assert lib.gp_predict_model_bytes(C.byref(k), _lib.GP_PREC_FP64, 100, 0) == 0

@@ -126,3 +126,39 @@ def test_full_size_sampled_rows(name, nrows):
         assert err <= TOL[prec]
         assert err_off <= TOL_OFF[prec]
         del out
+
+
+FP64_CASES = [
+    (333, 7, 3, True),
+    (2048 + 17, 48, 16, True),   # ragged last chunk
+    (1000, 64, 20, True),        # widest features of the form, two column groups
+    (1, 5, 1, True),
+    (2048, 32, 9, False),
+]
+
+
+@pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
+@pytest.mark.parametrize("case", FP64_CASES)
+def test_fp64_square_product_matches_oracle(case, kind):
+    """The FP64 form (low-noise regime): agreement to FP64 rounding of the sums."""
+    n, d, t, cond = case
+    X, th, V = _case(n, d, t, cond, seed=n + t + 1, kind=kind)
+    got = _run(th, X, V, "fp64")
+    ref = ok.khat_matmul(X, th, V.T).T
+    # error against the same sum of magnitudes: rounding is relative to |K| |V|, not to the result
+    scale = ok.khat_matmul(X, ok.Theta(th.ell, th.sf, th.noise, th.kind), np.abs(V).T).T
+    err = np.max(np.abs(got - ref) / scale)
+    print(f"fp64 case n={n} d={d} t={t} kind={kind}: err / |K||V| = {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("m", [1, 155])
+def test_fp64_cross_product_matches_oracle(m):
+    n, d, t = 3000, 48, 20
+    X, th, V = _case(n, d, t, True, seed=6)
+    Z = synth.query_molecule("c2", m, seed=m)[:, :d]
+    got = _run(th, X, V, "fp64", Z=Z)
+    ref = ok.cross_matmul(Z, X, th, V.T).T
+    scale = ok.cross_matmul(Z, X, th, np.abs(V).T).T
+    err = np.max(np.abs(got - ref) / scale)
+    assert err <= 1e-13
