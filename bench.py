@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--fit-c4", type=int, default=0, metavar="K",
                     help="training mode: K Adam steps (lr 0.05 on log theta, start l = 1, s_f = 1, "
                          "sigma^2 = 1e-2) on the n = 262,144, d = 48 model with t = 32 probes, and exit")
+    ap.add_argument("--noise-sweep", action="store_true",
+                    help="low-noise mode: mBCG (pivoted Cholesky rank 100, [y | 15 probes], tol 1e-6) at "
+                         "sigma^2 = 1e-2 .. 1e-8 with BF16x3, FP32 and FP64 products on two n = 16,384 "
+                         "data sets, true residuals from FP64 products; product timings at n = 131,072; exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,6 +138,9 @@ def main():
         return
     if args.fit_c4:
         fit_c4(args, synth, torch, dev, np)
+        return
+    if args.noise_sweep:
+        noise_sweep(gp, _lib, synth, torch, dev, np)
         return
 
     names = [("c3o", 917504), ("c3d", 131072)]
@@ -361,6 +368,67 @@ def fit_c4(args, synth, torch, dev, np):
         "first_step_s": res.seconds[0], "mll": res.mll, "mbcg_iters": res.iters,
         "final": {"lengthscale_min": float(th[:d].min()), "lengthscale_max": float(th[:d].max()),
                   "outputscale": float(th[d]), "noise": float(th[d + 1])}}}), flush=True)
+
+
+def noise_sweep(gp, _lib, synth, torch, dev, np):
+    """Where each product precision stops resolving K_hat (Sec. 3.2: rounding beyond the noise breaks
+    the solver).  Two n = 16,384 data sets: the ill-conditioned variant of the n = 65,536 workload's
+    layout, and the same layout with nearly repeated pairs of rows (lambda_min(K) ~ 1e-5)."""
+    n, t, rank, tol, max_iter = 16384, 15, 100, 1e-6, 1500
+    out = {"n": n, "probes": t, "rank": rank, "tol": tol, "max_iter": max_iter, "runs": []}
+    p = synth.make_problem("c2", n=n, cond_variant=True)
+    sets = [("ill_conditioned", p.X, p.y, p.ell), ("near_duplicate_pairs",) + synth.near_duplicate_pairs(n, 7)]
+    for label, Xh, yh, ell in sets:
+        X = torch.from_numpy(Xh).to(dev)
+        y = torch.from_numpy(yh).to(dev)
+        for noise in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+            k = gp.Kernel(ell, 1.0, noise)
+            pc = gp.pivchol(k, X, rank)
+            B = gp.probe_block(y, t, 5, noise, pc)
+            for prec in ("bf16x3", "fp32", "fp64"):
+                rec = {"data": label, "noise": noise, "precision": prec}
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                try:
+                    r = gp.mbcg(k, X, B, max_iter, tol, pc=pc, precision=prec, want_z0=False)
+                except _lib.GpError as e:
+                    rec.update(status="breakdown", error=str(e), seconds=time.perf_counter() - t0)
+                    out["runs"].append(rec)
+                    log(f"noise {label} {noise:.0e} {prec}: breakdown ({e})")
+                    continue
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                KU = gp.kmm(k, X, r.U[:1].contiguous(), precision="fp64")
+                true = float(torch.linalg.norm(KU[0] - y) / torch.linalg.norm(y))
+                rec.update(status="converged" if r.status == 0 else "max_iter", iters=int(r.iters.max()),
+                           y_iters=int(r.iters[0]), relres_max=float(r.relres.max()), true_relres_y=true,
+                           seconds=dt, ms_per_iter=dt / max(1, int(r.iters.max())) * 1e3)
+                out["runs"].append(rec)
+                log(f"noise {label} {noise:.0e} {prec}: {rec['status']} {rec['iters']} it, y: recurrence "
+                    f"{r.relres[0]:.1e} true {true:.1e}, {dt:.2f} s")
+            del pc, B
+        del X, y
+        torch.cuda.empty_cache()
+    # the three product forms at n = 131,072, t = 16
+    p = synth.make_problem("c3d")
+    X = torch.from_numpy(p.X).to(dev)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    V = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 3)).to(dev)
+    W = torch.empty_like(V)
+    nn = p.X.shape[0]
+    out["products_n131072_t16"] = {}
+    for prec in ("bf16x3", "fp32", "fp64"):
+        gp.kmm(k, X, V, precision=prec, out=W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            gp.kmm(k, X, V, precision=prec, out=W)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        out["products_n131072_t16"][prec] = {"ms": ms,
+                                             "tflops_nominal": 2.0 * nn * nn * (p.X.shape[1] + 16) / ms / 1e9}
+        log(f"product n={nn} t=16 {prec}: {ms:.2f} ms")
+    print(json.dumps({"noise_sweep": out}), flush=True)
 
 
 def altbbmm_leg(gp, synth, torch, dev, np):

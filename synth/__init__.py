@@ -181,6 +181,18 @@ def make_problem(name: str, n: Optional[int] = None, cond_variant: bool = False,
     return Problem(np.ascontiguousarray(X), y, ell, sf, cfg.noise, kind, mol, cfg, cond_variant)
 
 
+def near_duplicate_pairs(n: int, seed: int, jitter: float = 1e-3):
+    """The ill-conditioned variant of the n = 65,536 workload's layout at n // 2 rows, each row paired
+    with a copy moved by ``jitter`` of a lengthscale per feature (N(0, 1) directions).  Like the nearly
+    repeated pair features of molecular data, the pairs make K nearly singular (lambda_min ~ 1e-5 at
+    jitter 1e-3), so that the noise level decides the conditioning.  Returns (X, y, ell); the targets
+    of a pair are equal."""
+    p = make_problem("c2", n=n // 2, cond_variant=True, seed=seed)
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 100]))
+    X = np.vstack([p.X, p.X + jitter * p.ell * rng.standard_normal(p.X.shape)])
+    return np.ascontiguousarray(X), np.concatenate([p.y, p.y]), p.ell
+
+
 def random_block(n: int, t: int, seed: int) -> np.ndarray:
     """A dense (t, n) block of N(0,1) right-hand sides (column c is row c)."""
     return np.random.default_rng(np.random.SeedSequence([int(seed), 7])).standard_normal((t, n))

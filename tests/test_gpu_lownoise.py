@@ -22,24 +22,13 @@ def _gk(th):
     return gp.Kernel(th.ell, th.sf, th.noise, "matern52")
 
 
-def _near_duplicates(n, seed):
-    """Clustered rows (the ill-conditioned variant's lengthscales), each paired with a copy jittered by
-    1e-3 of a lengthscale per feature: like the nearly repeated pair features of molecular data, this
-    makes K nearly singular (lambda_min ~ 1e-5), so that the noise decides the conditioning."""
-    p = synth.make_problem("c2", n=n // 2, cond_variant=True, seed=seed)
-    rng = np.random.default_rng(seed + 100)
-    X = np.vstack([p.X, p.X + 1e-3 * p.ell * rng.standard_normal(p.X.shape)])
-    y = np.concatenate([p.y, p.y])
-    return X, y, p.ell
-
-
 @pytest.mark.parametrize("noise", [1e-5, 1e-7])
 def test_fp64_solves_reach_the_dense_solution_at_low_noise(noise):
     """mBCG with FP64 products reaches the FP64 limit (true residual ~ kappa * eps) at kappa ~ 1e7; the
     BF16x3 products stall orders of magnitude above it."""
     from paper_2109_09817_amd import gp
     n = 1536
-    X, y, ell = _near_duplicates(n, 4)
+    X, y, ell = synth.near_duplicate_pairs(n, 4)
     th = ok.Theta(ell, 1.0, noise)
     Kh = ok.khat(X, th)
     ev = np.linalg.eigvalsh(Kh)
@@ -73,7 +62,7 @@ def test_fp64_block_cg_at_low_noise():
     rank-revealing inverse of K_MM keeps from spoiling P^{-1/2}."""
     from paper_2109_09817_amd import gp
     n, s = 1200, 8
-    X, y, ell = _near_duplicates(n, 5)
+    X, y, ell = synth.near_duplicate_pairs(n, 5)
     th = ok.Theta(ell, 1.0, 1e-6)
     Kh = ok.khat(X, th)
     B = np.column_stack([y, np.random.default_rng(3).standard_normal((n, s - 1))])
