@@ -76,6 +76,7 @@ extern "C" {
 #define GP_OP_NYSTROM 9
 #define GP_OP_NYSTROM_APPLY 10
 #define GP_OP_BCG 11
+#define GP_OP_EXACT 12
 
 /*
  * ARD stationary kernel with r^2 = sum_j ((x_j - z_j) / l_j)^2 (Sec. 2.2;
@@ -340,6 +341,26 @@ int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
            const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
            double* W, int64_t ldw, int32_t* iters, double* relres,
            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_exact_mll_and_grad - the exact GP of the AltBBMM hyperparameter
+ * protocol (Sec. 3.2, Sec. 4: hyperparameters from a full GP on a random
+ * subset of the training molecules), dense FP64 on the device:
+ *   K_hat = L L^T (Cholesky), omega = K_hat^{-1} y,
+ *   mll = -1/2 y^T omega - 1/2 log|K_hat| - n/2 log 2 pi           (Eq. 2),
+ *   grad_j = 1/2 omega^T dK_hat_j omega - 1/2 tr(K_hat^{-1} dK_hat_j)
+ * over (log l_1 .. log l_d, log s_f, log sigma^2), the order of gp_kmm_grad.
+ * X: device n x d row-major FP64; y: device n.  mll: host.  grad: host d + 2,
+ * or NULL to skip the derivative sweep.  omega: device n, or NULL.
+ * Requires 1 <= n <= 65536, d <= 64.  Errors: GP_EINVAL, GP_ENOTPD (K_hat not
+ * numerically positive definite, e.g. repeated rows with sigma^2 = 0),
+ * GP_ENONFINITE, GP_EWORKSPACE, GP_EHIP.  Synchronous.  O(n^3) flops; the
+ * workspace holds two n x n FP64 matrices (K_hat's factor and its inverse).
+ * Workspace: gp_workspace_bytes(GP_OP_EXACT, n, 0, d, 0, 0, any precision).
+ */
+int gp_exact_mll_and_grad(const gp_kernel* kern, const double* X, const double* y, int64_t n,
+                          double* mll, double* grad, double* omega,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gp_workspace_bytes - device scratch needed by one call of `op`

@@ -33,6 +33,7 @@ GP_OP_PREDICT_RUN = 8
 GP_OP_NYSTROM = 9
 GP_OP_NYSTROM_APPLY = 10
 GP_OP_BCG = 11
+GP_OP_EXACT = 12
 
 
 class GpKernel(C.Structure):
@@ -89,6 +90,8 @@ PROTOTYPES = {
     "gp_nystrom_precond": (C.c_int, [C.POINTER(GpKernel), _P, _I64, C.POINTER(C.c_int64), _I32, _P, _P,
                                      _P, _SZ, _P]),
     "gp_nystrom_apply": (C.c_int, [_P, _P, _I64, _I32, _D, _P, _I32, _P, _P, _SZ, _P]),
+    "gp_exact_mll_and_grad": (C.c_int, [C.POINTER(GpKernel), _P, _P, _I64, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), _P, _P, _SZ, _P]),
     "gp_bcg": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _I64, _I32, _I32, _D, _P, _I64,
                          C.POINTER(_I32), C.POINTER(_D), _P, _SZ, _P]),
     "gp_workspace_bytes": (C.c_size_t, [_I32, _I64, _I64, _I32, _I32, _I32, _I32]),

@@ -12,7 +12,10 @@ gradient entries that ``gp_kmm_grad`` and ``gp_mll_and_grad`` return.
   Its forward runs preconditioner, probes, mBCG, stochastic Lanczos quadrature
   and the gradient sweep in one library call; backward scales the gradient
   estimate that call returned.
-* ``fit``: Adam on log theta against -L / n.
+* ``ExactMLL``: the exact log marginal likelihood of a dense Cholesky GP (the
+  AltBBMM protocol's subset model, Sec. 3.2, Sec. 4) and its exact gradient.
+* ``fit``: Adam on log theta against -L / n (BBMM estimates); ``fit_exact``:
+  the same on the exact GP.
 
 All arithmetic runs in libgpkmm's kernels; these classes only marshal.
 """
@@ -97,6 +100,24 @@ class MLL(torch.autograd.Function):
         return (go * g,) + (None,) * 9
 
 
+class ExactMLL(torch.autograd.Function):
+    """Exact log marginal likelihood L(theta) of the dense GP on (X, y) as a scalar tensor."""
+
+    @staticmethod
+    def forward(ctx, log_theta: torch.Tensor, X: torch.Tensor, y: torch.Tensor, kind: str = "matern52") -> torch.Tensor:
+        kern = kernel_from_log(log_theta, kind)
+        r = gp.exact_mll_and_grad(kern, X.detach(), y.detach(), with_grad=True)
+        ctx.save_for_backward(_like(r.grad, log_theta))
+        return _like(r.mll, log_theta)
+
+    @staticmethod
+    def backward(ctx, go: torch.Tensor):
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            raise NotImplementedError("ExactMLL: gradients flow to the hyperparameters only")
+        (g,) = ctx.saved_tensors
+        return go * g, None, None, None
+
+
 @dataclasses.dataclass
 class FitResult:
     log_theta: np.ndarray                 # final (d + 2)
@@ -124,6 +145,29 @@ def fit(X: torch.Tensor, y: torch.Tensor, log_theta0, steps: int = 50, lr: float
         opt.step()
         out.mll.append(float(mll.detach()))
         out.iters.append(_mll_iters(mll))
+        out.seconds.append(time.perf_counter() - t0)
+        if callback is not None:
+            callback(s, out)
+    out.log_theta = p.detach().numpy().copy()
+    return out
+
+
+def fit_exact(X: torch.Tensor, y: torch.Tensor, log_theta0, steps: int = 50, lr: float = 0.05,
+              kind: str = "matern52", callback=None) -> FitResult:
+    """Adam on log theta minimising -L/n of the exact GP (deterministic: no probes)."""
+    n = X.shape[0]
+    p = torch.tensor(np.asarray(log_theta0, dtype=np.float64), requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr)
+    out = FitResult(np.empty(0), [], [], [], [])
+    for s in range(steps):
+        t0 = time.perf_counter()
+        opt.zero_grad()
+        out.trajectory.append(p.detach().numpy().copy())
+        mll = ExactMLL.apply(p, X, y, kind)
+        (-mll / n).backward()
+        opt.step()
+        out.mll.append(float(mll.detach()))
+        out.iters.append(0)
         out.seconds.append(time.perf_counter() - t0)
         if callback is not None:
             callback(s, out)

@@ -275,6 +275,33 @@ def nystrom_apply(pc: Nystrom, V: torch.Tensor, out: Optional[torch.Tensor] = No
 
 
 @dataclasses.dataclass
+class ExactResult:
+    mll: float
+    grad: Optional[np.ndarray]     # (d + 2,): log l_1..log l_d, log s_f, log sigma^2
+    omega: Optional[torch.Tensor]  # (n,): K_hat^{-1} y
+
+
+def exact_mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, with_grad: bool = True,
+                       with_omega: bool = False, ws: Optional[torch.Tensor] = None) -> ExactResult:
+    """Exact (dense Cholesky) GP: the log marginal likelihood, its gradient and K_hat^{-1} y."""
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    _need(y, "y", (n,))
+    need = lib.gp_workspace_bytes(_lib.GP_OP_EXACT, n, 0, kern.d, 0, 0, _lib.GP_PREC_FP64)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, X.device)
+    mll = C.c_double(0.0)
+    g = np.zeros(kern.d + 2) if with_grad else None
+    om = torch.empty((n,), dtype=torch.float64, device=X.device) if with_omega else None
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_exact_mll_and_grad(C.byref(ks), X.data_ptr(), y.data_ptr(), n, C.byref(mll),
+                                         None if g is None else g.ctypes.data_as(C.POINTER(C.c_double)), _ptr(om),
+                                         ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return ExactResult(float(mll.value), g, om)
+
+
+@dataclasses.dataclass
 class BcgResult:
     W: torch.Tensor          # (s, n): K_hat^{-1} B
     iters: int

@@ -193,6 +193,16 @@ def near_duplicate_pairs(n: int, seed: int, jitter: float = 1e-3):
     return np.ascontiguousarray(X), np.concatenate([p.y, p.y]), p.ell
 
 
+def molecule_subset(mol: np.ndarray, count: int, seed: int) -> np.ndarray:
+    """Sorted row indices of ``count`` molecules drawn uniformly without replacement (the molecule ids
+    ``mol`` of a clustered layout)."""
+    ids = np.unique(mol)
+    if count > ids.size:
+        raise ValueError(f"{count} molecules requested, {ids.size} available")
+    pick = np.random.default_rng(np.random.SeedSequence([int(seed), 13])).choice(ids, count, replace=False)
+    return np.flatnonzero(np.isin(mol, pick))
+
+
 def random_block(n: int, t: int, seed: int) -> np.ndarray:
     """A dense (t, n) block of N(0,1) right-hand sides (column c is row c)."""
     return np.random.default_rng(np.random.SeedSequence([int(seed), 7])).standard_normal((t, n))

@@ -158,3 +158,26 @@ def test_fp64_products_are_limited_to_the_solves(lib):
     assert lib.gp_workspace_bytes(_lib.GP_OP_MLL, 1000, 0, 48, 16, 10, _lib.GP_PREC_FP64) == 0
     assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, 1000, 0, 65, 16, 0, _lib.GP_PREC_FP64) == 0  # d <= 64
     assert lib.gp_predict_model_bytes(C.byref(k), _lib.GP_PREC_FP64, 100, 0) == 0
+
+
+def test_exact_gp_entry_point_validates_on_the_host(lib):
+    from paper_2109_09817_amd import _lib
+    k, keep = _kernel()
+    fake = 4096  # never dereferenced: validation fails first
+    mll = C.c_double(0.0)
+    g = np.zeros(6)
+    gp_ = g.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.gp_exact_mll_and_grad(C.byref(k), None, fake, 10, C.byref(mll), gp_, None, None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_exact_mll_and_grad(C.byref(k), fake, fake, 0, C.byref(mll), gp_, None, None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_exact_mll_and_grad(C.byref(k), fake, fake, 65537, C.byref(mll), gp_, None, None, 0,
+                                     None) == _lib.GP_EINVAL
+    k65, keep65 = _kernel(d=65)
+    assert lib.gp_exact_mll_and_grad(C.byref(k65), fake, fake, 10, C.byref(mll), None, None, None, 0,
+                                     None) == _lib.GP_EINVAL
+    assert lib.gp_exact_mll_and_grad(C.byref(k), fake, fake, 10, C.byref(mll), gp_, None, None, 0,
+                                     None) == _lib.GP_EWORKSPACE
+    # two n x n FP64 matrices dominate the workspace
+    b = lib.gp_workspace_bytes(_lib.GP_OP_EXACT, 8192, 0, 48, 0, 0, _lib.GP_PREC_FP64)
+    assert 2 * 8192 * 8192 * 8 <= b < 1.1 * 2 * 8192 * 8192 * 8
+    assert lib.gp_workspace_bytes(_lib.GP_OP_EXACT, 65537, 0, 48, 0, 0, 1) == 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_EXACT, 100, 0, 65, 0, 0, 1) == 0
