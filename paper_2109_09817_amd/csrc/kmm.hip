@@ -42,7 +42,8 @@ namespace gpk {
 constexpr int kFlush = 32;  // 32-point chunks accumulated in FP32 before the FP64 flush
 constexpr int kF64MaxD = 64;   // FP64 form: features held in registers
 constexpr int kF64Chunk = 32;  // FP64 form: points per LDS chunk
-constexpr int kF64Cols = 16;   // FP64 form: V columns per workgroup
+constexpr int kF64Cols = 64;   // FP64 form: V columns per pass
+constexpr int kF64Rows = 64;   // FP64 form: output rows per workgroup
 
 // The profile m(r) from S = r^2 scaled as above.  ACCURATE replaces the raw
 // v_sqrt_f32 by v_rsq_f32 plus one Newton step on the residual S - u^2; the raw
@@ -771,11 +772,15 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
 //
 // The low-noise regime (sigma^2 down to 1e-8, Sec. 3.2 and Sec. 4) needs K_hat V
 // to FP64 accuracy.  MI355X's FP64 matrix-core peak equals its FP64 vector peak,
-// so this form runs on the VALU: each thread owns one output row (its scaled
-// features in registers); 32-point chunks of the b stream and of V are staged in
-// LDS; r^2 = n_a + n_b - 2 x_a.x_b and the profile are evaluated in FP64; each
-// row sums sequentially over b (deterministic).  The diagonal entry is exactly
-// s_f (m(0) = 1) and sigma^2 V is added exactly.
+// so this form runs on the VALU.  A workgroup owns 64 output rows (lane = row,
+// its scaled features in registers) and up to 64 columns; per 32-point chunk of
+// the b stream (staged in LDS with its V values) each kernel entry is evaluated
+// once: wave q takes points 8q..8q+7 (r^2 = n_a + n_b - 2 x_a.x_b and the
+// profile in FP64) into an LDS tile M; then the waves share M V, one 16-column
+// group each when there are more than two groups, otherwise the groups times a
+// split of the 32 points, and the point-split partials are added in wave order
+// at the end (deterministic).  The diagonal entry is exactly s_f (m(0) = 1) and
+// sigma^2 V is added exactly.
 
 // sc64[f] = feature scale (thread f < d); nrm[p] = |x_p (.) sc|^2 for p < rows.
 __global__ void prep_fp64_kernel(const double* __restrict__ X, int64_t rows, int d, Scale sc,
@@ -800,73 +805,111 @@ __global__ __launch_bounds__(256) void sweep_fp64_kernel(const double* __restric
                                                          double* __restrict__ out, int64_t ldo) {
   __shared__ double Bs[kF64Chunk][DP];
   __shared__ double Ns[kF64Chunk];
-  __shared__ double Vs[kF64Cols][kF64Chunk];
-  __shared__ double Ss[DP];
+  __shared__ double Xt[DP][kF64Rows];  // the workgroup's scaled rows, feature-major
+  // V values of the chunk [c][j], then the entries [j][row]; after the sweep the
+  // same array holds the reduction rows [wave][c][row]
+  __shared__ double VM[kF64Cols * kF64Chunk + kF64Chunk * kF64Rows];
+  static_assert(kF64Cols * kF64Chunk + kF64Chunk * kF64Rows >= 4 * 16 * kF64Rows, "reduction rows");
+  double* const Vs = VM;
+  double* const Ms = VM + kF64Cols * kF64Chunk;
   const int tid = threadIdx.x;
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t a0 = (int64_t)blockIdx.x * kF64Rows;
+  const int64_t a = a0 + lane;
   const int c0 = blockIdx.y * kF64Cols;
-  for (int f = tid; f < DP; f += blockDim.x) Ss[f] = f < d ? sc64[f] : 0.0;
-  __syncthreads();
+  const int tc = t - c0 < kF64Cols ? t - c0 : kF64Cols;  // columns of this pass
+  const int groups = (tc + 15) / 16;                     // 16-column groups
+  // phase-2 roles: column group grp, points [j0, j0 + jcount) of each chunk
+  const int gsplit = groups > 2 ? 4 : groups;  // groups per wave set
+  const int grp = wave % gsplit;
+  const int parts = 4 / gsplit;                // point splits
+  const int jcount = kF64Chunk / parts;
+  const int pj0 = (wave / gsplit) * jcount;
+  for (int e = tid; e < kF64Rows * DP; e += blockDim.x) {
+    const int r = e / DP, f = e - r * DP;
+    Xt[f][r] = (a0 + r < m && f < d) ? Xa[(a0 + r) * d + f] * sc64[f] : 0.0;
+  }
   const bool live = a < m;
-  double xa[DP];
-#pragma unroll
-  for (int f = 0; f < DP; ++f) xa[f] = (live && f < d) ? Xa[a * d + f] * Ss[f] : 0.0;
   const double naa = live ? na[a] : 0.0;
-  double acc[kF64Cols];
+  double acc[16];
 #pragma unroll
-  for (int c = 0; c < kF64Cols; ++c) acc[c] = 0.0;
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
   for (int64_t b0 = 0; b0 < n; b0 += kF64Chunk) {
     __syncthreads();
     for (int e = tid; e < kF64Chunk * DP; e += blockDim.x) {
       const int j = e / DP, f = e - j * DP;
       const int64_t b = b0 + j;
-      Bs[j][f] = (b < n && f < d) ? Xb[b * d + f] * Ss[f] : 0.0;
+      Bs[j][f] = (b < n && f < d) ? Xb[b * d + f] * sc64[f] : 0.0;
     }
     for (int e = tid; e < kF64Chunk; e += blockDim.x) Ns[e] = b0 + e < n ? nb[b0 + e] : 0.0;
     for (int e = tid; e < kF64Chunk * kF64Cols; e += blockDim.x) {
       const int c = e / kF64Chunk, j = e - c * kF64Chunk;
       const int64_t b = b0 + j;
-      Vs[c][j] = (b < n && c0 + c < t) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
+      Vs[c * kF64Chunk + j] = (b < n && c < tc) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
     }
     __syncthreads();
-    const int jn = n - b0 < kF64Chunk ? (int)(n - b0) : kF64Chunk;
-    // two points per step, each dot product as four interleaved partial sums:
-    // eight independent FMA chains instead of one chain of DP
-    for (int j = 0; j < jn; j += 2) {
-      double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
+    // phase 1: entries (row lane, points 8 wave .. 8 wave + 7): one feature of the
+    // row per LDS read, applied to eight points (broadcast reads), eight FMA chains
+    const int jb = 8 * wave;
+    double dot[8];
 #pragma unroll
-      for (int f = 0; f < DP; ++f) {
-        p0[f & 3] = fma(xa[f], Bs[j][f], p0[f & 3]);
-        p1[f & 3] = fma(xa[f], Bs[j + 1][f], p1[f & 3]);  // row j + 1 < kF64Chunk exists (zeros past n)
+    for (int q = 0; q < 8; ++q) dot[q] = 0.0;
+#pragma unroll 2
+    for (int f = 0; f < DP; f += 2) {
+      const double x0 = Xt[f][lane], x1 = Xt[f + 1][lane];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dot[q] = fma(x1, Bs[jb + q][f + 1], fma(x0, Bs[jb + q][f], dot[q]));
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double S = fmax(naa + Ns[jb + q] - 2.0 * dot[q], 0.0);
+      const int64_t b = b0 + jb + q;
+      double mv;
+      if (b >= n) {
+        mv = 0.0;
+      } else if (square && b == a) {
+        mv = 1.0;
+      } else if constexpr (KIND == GP_MATERN52) {
+        const double u = sqrt(S);
+        mv = fma(u, fma(u, 1.0 / 3.0, 1.0), 1.0) * exp(-u);
+      } else {
+        mv = exp(-0.5 * S);
       }
-      double mv[2];
+      Ms[(jb + q) * kF64Rows + lane] = mv;
+    }
+    __syncthreads();
+    // phase 2: acc[c] += sum over this wave's points of M[row][j] V[j][16 grp + c]
+    if (grp < groups) {
+      for (int j = pj0; j < pj0 + jcount; ++j) {
+        const double mj = Ms[j * kF64Rows + lane];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const double* pp = q == 0 ? p0 : p1;
-        const double dot = (pp[0] + pp[1]) + (pp[2] + pp[3]);
-        const double S = fmax(naa + Ns[j + q] - 2.0 * dot, 0.0);
-        if (j + q >= jn) {
-          mv[q] = 0.0;
-        } else if (square && b0 + j + q == a) {
-          mv[q] = 1.0;
-        } else if constexpr (KIND == GP_MATERN52) {
-          const double u = sqrt(S);
-          mv[q] = fma(u, fma(u, 1.0 / 3.0, 1.0), 1.0) * exp(-u);
-        } else {
-          mv[q] = exp(-0.5 * S);
-        }
+        for (int c = 0; c < 16; ++c) acc[c] = fma(mj, Vs[(16 * grp + c) * kF64Chunk + j], acc[c]);
       }
-#pragma unroll
-      for (int c = 0; c < kF64Cols; ++c) acc[c] = fma(mv[1], Vs[c][j + 1], fma(mv[0], Vs[c][j], acc[c]));
     }
   }
-  if (!live) return;
+  // point-split partials of one group are added in wave order
+  if (parts > 1) {
+    __syncthreads();
+    double* const red_all = VM;  // [wave][c][row]
 #pragma unroll
-  for (int c = 0; c < kF64Cols; ++c) {
-    if (c0 + c < t) {
+    for (int c = 0; c < 16; ++c) red_all[(wave * 16 + c) * kF64Rows + lane] = acc[c];
+    __syncthreads();
+    if (wave >= gsplit) return;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      double s = 0.0;
+      for (int pp = 0; pp < parts; ++pp) s += red_all[((pp * gsplit + grp) * 16 + c) * kF64Rows + lane];
+      acc[c] = s;
+    }
+  }
+  if (!live || grp >= groups) return;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = c0 + 16 * grp + c;
+    if (col < t) {
       double y = sf * acc[c];
-      if (square) y = fma(noise, V[(int64_t)(c0 + c) * ldv + a], y);
-      out[(int64_t)(c0 + c) * ldo + a] = y;
+      if (square) y = fma(noise, V[(int64_t)col * ldv + a], y);
+      out[(int64_t)col * ldo + a] = y;
     }
   }
 }
@@ -893,7 +936,7 @@ static void launch_fp64(int kind, dim3 grid, const KmmPlan& p, const double* V, 
 static hipError_t sweep_fp64(const KmmPlan& p, const double* V, int64_t ldv, int t, double* out, int64_t ldo,
                              hipStream_t st) {
   if (!p.x64 || !p.z64 || !V || !out || t < 1) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((p.m + 255) / 256), (unsigned)((t + kF64Cols - 1) / kF64Cols));
+  dim3 grid((unsigned)((p.m + kF64Rows - 1) / kF64Rows), (unsigned)((t + kF64Cols - 1) / kF64Cols));
   const int dp = (p.d + 15) / 16 * 16;
   switch (dp) {
     case 16: launch_fp64<16>(p.kind, grid, p, V, ldv, t, out, ldo, st); break;
