@@ -80,46 +80,6 @@ __global__ __launch_bounds__(256) void form_khat_kernel(const double* __restrict
 
 // ---------------------------------------------------------------- Cholesky
 
-// Unblocked Cholesky of the diagonal block A[j0.., j0..] (jb <= 64 rows) in
-// LDS; the block outside jb is padded with the identity.  Writes L (lower,
-// zero above the diagonal).  A pivot that is not positive records its global
-// index + 1 in *info (the first one only) and continues with 1, so that every
-// later step stays finite and bounded.
-__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t j0, int jb,
-                                                    int* __restrict__ info) {
-  __shared__ double Ls[kEb][kEb + 1];
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-    const int r = e / kEb, c = e % kEb;
-    Ls[r][c] = (r < jb && c < jb) ? A[(j0 + r) * n + j0 + c] : (r == c ? 1.0 : 0.0);
-  }
-  for (int k = 0; k < kEb; ++k) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double p = Ls[k][k];
-      if (!(p > 0.0) || !isfinite(p)) {
-        if (bad == 0) bad = (int)(j0 + k + 1);
-        p = 1.0;
-      }
-      Ls[k][k] = sqrt(p);
-    }
-    __syncthreads();
-    for (int r = k + 1 + threadIdx.x; r < kEb; r += 256) Ls[r][k] /= Ls[k][k];
-    __syncthreads();
-    for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-      const int r = e / kEb, c = e % kEb;
-      if (c > k && c <= r) Ls[r][c] -= Ls[r][k] * Ls[c][k];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-    const int r = e / kEb, c = e % kEb;
-    if (r < jb && c < jb) A[(j0 + r) * n + j0 + c] = c <= r ? Ls[r][c] : 0.0;
-  }
-  if (threadIdx.x == 0 && bad != 0 && *info == 0) *info = bad;
-}
-
 // Load the factored diagonal block L[i0.., i0..] (ib rows) into LDS, identity-padded.
 __device__ __forceinline__ void load_diag_block(const double* __restrict__ L, int64_t n, int64_t i0, int ib,
                                                 double (*Ls)[kEb + 1]) {
@@ -129,21 +89,85 @@ __device__ __forceinline__ void load_diag_block(const double* __restrict__ L, in
   }
 }
 
-// Dinv = L_ii^{-1} (64 x 64, row-major; identity beyond ib) by forward
-// substitution against the unit vectors: thread j forms column j in LDS.
-__global__ __launch_bounds__(64) void trtri_diag_kernel(const double* __restrict__ L, int64_t n, int64_t i0, int ib,
-                                                        double* __restrict__ Dinv) {
+// Xs = Ls^{-1} for a lower-triangular 64 x 64 Ls in LDS, 256 threads: lanes
+// 4j..4j+3 form column j by forward substitution against e_j, lane s summing
+// the terms m = s (mod 4) and keeping in Xs only the entries of its own class,
+// so that each lane reads back what it wrote; the four partial sums meet by
+// shuffles.  Ends with a barrier; Xs is complete (zero above the diagonal).
+__device__ __forceinline__ void diag_inverse(const double (*Ls)[kEb + 1], double (*Xs)[kEb + 1]) {
+  const int j = threadIdx.x >> 2, sub = threadIdx.x & 3;
+  for (int r = 0; r < kEb; ++r) {
+    if (r < j) {
+      if ((r & 3) == sub) Xs[r][j] = 0.0;
+      continue;  // uniform over the four lanes of column j
+    }
+    double part = 0.0;
+    for (int m = j + ((sub - j) & 3); m < r; m += 4) part = fma(Ls[r][m], Xs[m][j], part);
+    part += __shfl_xor(part, 1);
+    part += __shfl_xor(part, 2);
+    const double x = ((r == j ? 1.0 : 0.0) - part) / Ls[r][r];
+    if ((r & 3) == sub) Xs[r][j] = x;
+  }
+  __syncthreads();
+}
+
+// Unblocked Cholesky of the diagonal block A[j0.., j0..] (jb <= 64 rows) in
+// LDS, the block outside jb padded with the identity; writes L (lower, zero
+// above the diagonal) and, when Dinv is given, L^{-1} (64 x 64 row-major).  A
+// pivot that is not positive records its global index + 1 in *info (the first
+// one only) and continues with 1, so that every later step stays finite and
+// bounded.
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t n, int64_t j0, int jb,
+                                                         int* __restrict__ info, double* __restrict__ Dinv) {
   __shared__ double Ls[kEb][kEb + 1];
   __shared__ double Xs[kEb][kEb + 1];
-  load_diag_block(L, n, i0, ib, Ls);
-  __syncthreads();
-  const int j = threadIdx.x;
-  for (int r = 0; r < kEb; ++r) {
-    double s = r == j ? 1.0 : 0.0;
-    for (int m = j; m < r; ++m) s -= Ls[r][m] * Xs[m][j];
-    Xs[r][j] = r < j ? 0.0 : s / Ls[r][r];
+  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
+    const int r = e / kEb, c = e % kEb;
+    Ls[r][c] = (r < jb && c < jb) ? A[(j0 + r) * n + j0 + c] : (r == c ? 1.0 : 0.0);
   }
-  for (int r = 0; r < kEb; ++r) Dinv[r * kEb + j] = Xs[r][j];
+  int bad = 0;  // thread 0 only
+  for (int k = 0; k < kEb; ++k) {
+    __syncthreads();
+    double p = Ls[k][k];
+    if (!(p > 0.0) || !isfinite(p)) {
+      if (threadIdx.x == 0 && bad == 0) bad = (int)(j0 + k + 1);
+      p = 1.0;
+    }
+    const double piv = sqrt(p);
+    if ((int)threadIdx.x > k && (int)threadIdx.x < kEb) Ls[threadIdx.x][k] /= piv;
+    __syncthreads();
+    if (threadIdx.x == 0) Ls[k][k] = piv;
+#pragma unroll
+    for (int it = 0; it < kEb * kEb / 256; ++it) {
+      const int e = threadIdx.x + 256 * it;
+      const int r = e / kEb, c = e % kEb;
+      if (c > k && c <= r) Ls[r][c] -= Ls[r][k] * Ls[c][k];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
+    const int r = e / kEb, c = e % kEb;
+    if (c > r) Ls[r][c] = 0.0;
+    if (r < jb && c < jb) A[(j0 + r) * n + j0 + c] = c <= r ? Ls[r][c] : 0.0;
+  }
+  if (threadIdx.x == 0 && bad != 0 && *info == 0) *info = bad;
+  if (!Dinv) return;
+  __syncthreads();
+  diag_inverse(Ls, Xs);
+  for (int e = threadIdx.x; e < kEb * kEb; e += 256) Dinv[e] = Xs[e / kEb][e % kEb];
+}
+
+// Dinv + 64 * 64 * bi = L_ii^{-1} for every diagonal block bi (one workgroup each).
+__global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* __restrict__ L, int64_t n,
+                                                           double* __restrict__ Dinv) {
+  __shared__ double Ls[kEb][kEb + 1];
+  __shared__ double Xs[kEb][kEb + 1];
+  const int64_t i0 = (int64_t)blockIdx.x * kEb;
+  load_diag_block(L, n, i0, (int)(n - i0 < kEb ? n - i0 : kEb), Ls);
+  __syncthreads();
+  diag_inverse(Ls, Xs);
+  double* D = Dinv + (int64_t)blockIdx.x * kEb * kEb;
+  for (int e = threadIdx.x; e < kEb * kEb; e += 256) D[e] = Xs[e / kEb][e % kEb];
 }
 
 // ---------------------------------------------------------------- tile updates
@@ -157,8 +181,8 @@ __global__ __launch_bounds__(64) void trtri_diag_kernel(const double* __restrict
 // nrt, otherwise the nrt x nct rectangle.  Output rows and columns at or beyond
 // n are skipped (their operands read as 0).  Every operand is staged in LDS
 // before the tile is written, so C's tile may be one of the operand tiles
-// (never another workgroup's).  Each thread owns a 4 x 4 block (rows tr + 16 i,
-// columns tc + 16 j).
+// (never another workgroup's).  Each thread owns a 4 x 4 block (rows 4 tr + i,
+// columns 4 tc + j), so that its operands are two 16-byte LDS reads per side.
 template <bool PT, bool QT, bool LOWER, bool ASSIGN>
 __global__ __launch_bounds__(256) void tile_update_kernel(const double* Pm, int64_t ldp, int64_t pfix, int64_t p0,
                                                           const double* Qm, int64_t ldq, int64_t qfix, int64_t q0,
@@ -213,9 +237,9 @@ __global__ __launch_bounds__(256) void tile_update_kernel(const double* Pm, int6
   for (int k = 0; k < kEb; ++k) {
     double a[4], q[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = Ps[k][tr + 16 * i];
+    for (int i = 0; i < 4; ++i) a[i] = Ps[k][4 * tr + i];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) q[j] = Qs[k][tc + 16 * j];
+    for (int j = 0; j < 4; ++j) q[j] = Qs[k][4 * tc + j];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -223,11 +247,11 @@ __global__ __launch_bounds__(256) void tile_update_kernel(const double* Pm, int6
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t row = R + tr + 16 * i;
+    const int64_t row = R + 4 * tr + i;
     if (row >= n) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t col = Cc + tc + 16 * j;
+      const int64_t col = Cc + 4 * tc + j;
       if (col >= n) continue;
       if (ASSIGN)
         Cm[row * n + col] = acc[i][j];
@@ -255,14 +279,12 @@ static int ntiles(int64_t len) { return (int)((len + kEb - 1) / kEb); }
 static hipError_t cholesky(double* A, int64_t n, int* info, double* Dinv, hipStream_t st) {
   for (int64_t j0 = 0; j0 < n; j0 += kEb) {
     const int jb = (int)std::min<int64_t>(kEb, n - j0);
-    potf2_kernel<<<1, 256, 0, st>>>(A, n, j0, jb, info);
+    const int64_t rest = n - j0 - jb;
+    potrf_diag_kernel<<<1, 256, 0, st>>>(A, n, j0, jb, info, rest > 0 ? Dinv : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t rest = n - j0 - jb;
     if (rest <= 0) break;
     // L21 = A21 L11^{-T} = A21 Dinv^T (jb = 64 here: only the last block is narrower)
-    trtri_diag_kernel<<<1, kEb, 0, st>>>(A, n, j0, jb, Dinv);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     e = tile_update<false, true, false, true>(A, n, -1, j0, Dinv, kEb, 0, 0, A, n, jb, j0 + jb, j0, ntiles(rest), 1,
                                               st);
     if (e != hipSuccess) return e;
@@ -291,11 +313,8 @@ static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv
   if (e != hipSuccess) return e;
   // The diagonal blocks' inverses, kept for both passes: block bi at Dinv + 64 * 64 * bi.
   const int64_t nb = (n + kEb - 1) / kEb;
-  for (int64_t bi = 0; bi < nb; ++bi) {
-    const int64_t i0 = bi * kEb;
-    trtri_diag_kernel<<<1, kEb, 0, st>>>(L, n, i0, (int)std::min<int64_t>(kEb, n - i0), Dinv + bi * kEb * kEb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  trtri_blocks_kernel<<<(unsigned)nb, 256, 0, st>>>(L, n, Dinv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // forward, right-looking: X_i = L_ii^{-1} B_i on columns [0, i0 + ib); then
   // B_below -= L_below,i X_i on the same columns
   for (int64_t bi = 0; bi < nb; ++bi) {
