@@ -109,6 +109,11 @@ def main():
     ap.add_argument("--fit-c4", type=int, default=0, metavar="K",
                     help="training mode: K Adam steps (lr 0.05 on log theta, start l = 1, s_f = 1, "
                          "sigma^2 = 1e-2) on the n = 262,144, d = 48 model with t = 32 probes, and exit")
+    ap.add_argument("--profile-exact", type=int, default=0, metavar="K",
+                    help="profiling mode: K exact-GP evaluations (gp_exact_mll_and_grad) on the 50-molecule "
+                         "subset of the n = 131,072 model, and exit")
+    ap.add_argument("--profile-fp64", type=int, default=0, metavar="K",
+                    help="profiling mode: K FP64 products K_hat V at n = 131,072 for t = 16 and t = 50, and exit")
     ap.add_argument("--noise-sweep", action="store_true",
                     help="low-noise mode: mBCG (pivoted Cholesky rank 100, [y | 15 probes], tol 1e-6) at "
                          "sigma^2 = 1e-2 .. 1e-8 with BF16x3, FP32 and FP64 products on two n = 16,384 "
@@ -143,6 +148,12 @@ def main():
         return
     if args.noise_sweep:
         noise_sweep(gp, _lib, synth, torch, dev, np)
+        return
+    if args.profile_exact:
+        profile_exact(args, gp, synth, torch, dev, np)
+        return
+    if args.profile_fp64:
+        profile_fp64(args, gp, synth, torch, dev)
         return
 
     names = [("c3o", 917504), ("c3d", 131072)]
@@ -348,6 +359,44 @@ def profile_grad(args, gp, synth, torch, dev, np):
         g = gp.kmm_grad(k, X, U, W, w, precision="bf16x3")
         ms.append((time.perf_counter() - t0) * 1e3)
     print(json.dumps({"profile_grad": {"call_ms": ms, "grad0": float(g[0])}}), flush=True)
+
+
+def profile_exact(args, gp, synth, torch, dev, np):
+    """K exact-GP evaluations (mll, gradient) on the protocol's subset: 50 molecules of the n = 131,072 model."""
+    p = synth.make_problem("c3d")
+    sub = synth.molecule_subset(p.mol, 50, p.cfg.seed)
+    X = torch.from_numpy(np.ascontiguousarray(p.X[sub])).to(dev)
+    y = torch.from_numpy(np.ascontiguousarray(p.y[sub])).to(dev)
+    k = gp.Kernel(np.ones(p.X.shape[1]), 1.0, 1e-2)
+    ms = []
+    for _ in range(args.profile_exact):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gp.exact_mll_and_grad(k, X, y)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    print(json.dumps({"profile_exact": {"n": int(X.shape[0]), "call_ms": ms, "mll": r.mll}}), flush=True)
+
+
+def profile_fp64(args, gp, synth, torch, dev):
+    """K FP64 products on the n = 131,072 model at t = 16 (mBCG block) and t = 50 (block CG block)."""
+    p = synth.make_problem("c3d")
+    X = torch.from_numpy(p.X).to(dev)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    n = p.X.shape[0]
+    out = {}
+    for t in (16, 50):
+        V = torch.from_numpy(synth.random_block(n, t, 3)).to(dev)
+        W = torch.empty_like(V)
+        ms = []
+        for _ in range(args.profile_fp64):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gp.kmm(k, X, V, precision="fp64", out=W)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        out[f"t{t}_call_ms"] = ms
+    print(json.dumps({"profile_fp64": out}), flush=True)
 
 
 def fit_c4(args, synth, torch, dev, np):
