@@ -248,47 +248,10 @@ def main():
         }
         log(f"fp32 step: {(t3 - t2) * 1e3:.0f} ms")
 
-    # sampled rows of the product against the FP64 oracle, at the full size
-    from oracle import kernel as ok
-    q = probs["c3o"]
-    p = q["p"]
-    th = ok.Theta(p.ell, p.sf, p.noise)
-    V = synth.random_block(p.X.shape[0], t_cols, 3)
-    Vg = torch.from_numpy(V).to(dev)
-    rows = np.random.default_rng(0).choice(p.X.shape[0], 64, replace=False)
-    acc = {}
-    for prec in ("bf16x3", "fp32"):
-        W = gp.kmm(q["k"], q["X"], Vg, precision=prec)
-        torch.cuda.synchronize()
-        got = W.cpu().numpy()[:, rows]
-        ref = ok.khat_matmul(p.X, th, V.T, rows=rows).T
-        diag = (th.sf + th.noise) * V[:, rows]
-        acc[prec] = {
-            "rel_err": float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))),
-            "rel_err_offdiag": float(np.max(np.linalg.norm((got - diag) - (ref - diag), axis=1)
-                                            / np.linalg.norm(ref - diag, axis=1))),
-        }
-        del W
-    extra["kmm_vs_oracle_sampled_rows"] = acc
-
     cpu = None
     if not args.no_cpu:
-        R = 512
-        crow = np.random.default_rng(1).choice(p.X.shape[0], R, replace=False)
-        t4 = time.perf_counter()
-        ok.khat_matmul(p.X, th, V.T, rows=crow, block=128)
-        t5 = time.perf_counter()
-        fl = 2.0 * R * p.X.shape[0] * (p.X.shape[1] + t_cols)
-        try:
-            from threadpoolctl import threadpool_info
-            blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:
-            blas = None
-        cpu = {"value": fl / (t5 - t4) / 1e12, "unit": "TFLOP/s", "cores": blas or 1, "kind": "oracle",
-               "sample": f"FP64 oracle K_hat V for {R} sampled rows of the n=917,504 model (t={t_cols}); "
-                         f"{t5 - t4:.1f} s; the oracle's product runs on {blas} BLAS threads of "
-                         f"{os.cpu_count()} host cores, its distances (scipy cdist) on one of them"}
-        log(f"cpu baseline: {cpu['value']:.3e} TFLOP/s in {t5 - t4:.1f}s")
+        cpu, extra["kmm_vs_oracle_sampled_rows"], extra["cpu_vs_gpu_ops"] = cpu_baseline_leg(
+            gp, synth, torch, dev, np, probs["c3o"], t_cols)
 
     if not args.no_serve:
         extra["serving"] = serve_leg(args, gp, synth, torch, dev, np)
@@ -524,6 +487,89 @@ def altbbmm_leg(gp, synth, torch, dev, np):
         del pc, res, plain, Bd, X
         torch.cuda.empty_cache()
     return out
+
+
+def cpu_baseline_leg(gp, synth, torch, dev, np, q, t_cols):
+    """The FP64 oracle timed on the host cores beside the GPU (the only place the benchmark runs it):
+    its K_hat V on 512 sampled rows of the n = 917,504 model (the reported baseline, and the GPU
+    products' error on those rows), then two whole operations at n = 2,048 (the n = 2,048, d = 32
+    workload): the exact (dense Cholesky) mll and gradient, and one BBMM estimate (rank-20 pivoted
+    Cholesky, 8 probes, 30 iterations), each against the library's."""
+    from oracle import bbmm as obbmm, exact as oexact, kernel as ok
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = None
+    p = q["p"]
+    th = ok.Theta(p.ell, p.sf, p.noise)
+    n = p.X.shape[0]
+    V = synth.random_block(n, t_cols, 3)
+    R = 512
+    rows = np.random.default_rng(1).choice(n, R, replace=False)
+    t0 = time.perf_counter()
+    ref = ok.khat_matmul(p.X, th, V.T, rows=rows, block=128).T
+    t1 = time.perf_counter()
+    fl = 2.0 * R * n * (p.X.shape[1] + t_cols)
+    cpu = {"value": fl / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": blas or 1, "kind": "oracle",
+           "sample": f"FP64 oracle K_hat V for {R} sampled rows of the n=917,504 model (t={t_cols}); "
+                     f"{t1 - t0:.1f} s; the oracle's product runs on {blas} BLAS threads of "
+                     f"{os.cpu_count()} host cores, its distances (scipy cdist) on one of them"}
+    log(f"cpu baseline: {cpu['value']:.3e} TFLOP/s in {t1 - t0:.1f}s")
+    Vg = torch.from_numpy(V).to(dev)
+    diag = (th.sf + th.noise) * V[:, rows]
+    acc = {}
+    for prec in ("bf16x3", "fp32"):
+        W = gp.kmm(q["k"], q["X"], Vg, precision=prec)
+        torch.cuda.synchronize()
+        got = W.cpu().numpy()[:, rows]
+        acc[prec] = {
+            "rel_err": float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))),
+            "rel_err_offdiag": float(np.max(np.linalg.norm((got - diag) - (ref - diag), axis=1)
+                                            / np.linalg.norm(ref - diag, axis=1))),
+        }
+        del W
+    ops = []
+    c1 = synth.make_problem("c1")
+    th1 = ok.Theta(c1.ell, c1.sf, c1.noise)
+    k1 = gp.Kernel(c1.ell, c1.sf, c1.noise)
+    X1 = torch.from_numpy(c1.X).to(dev)
+    y1 = torch.from_numpy(c1.y).to(dev)
+    n1 = c1.X.shape[0]
+
+    def gpu_time(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ta) / reps, out
+
+    t0 = time.perf_counter()
+    g_ref = oexact.mll_grad(c1.X, c1.y, th1)
+    m_ref = oexact.cholesky_gp(c1.X, c1.y, th1)["mll"]
+    t1 = time.perf_counter()
+    tg, r = gpu_time(lambda: gp.exact_mll_and_grad(k1, X1, y1))
+    ops.append({"op": "exact mll + gradient (dense Cholesky)", "n": n1, "d": int(c1.X.shape[1]),
+                "cpu_s": t1 - t0, "gpu_s": tg, "gpu_over_cpu_speed": (t1 - t0) / tg,
+                "mll_rel_diff": abs(r.mll - m_ref) / abs(m_ref),
+                "grad_max_abs_diff": float(np.max(np.abs(r.grad - g_ref)))})
+    cfg = synth.CONFIGS["c1"]
+    t0 = time.perf_counter()
+    piv = [int(v) for v in gp.pivchol(k1, X1, cfg.rank).pivots]
+    o = obbmm.mll_and_grad_estimate(c1.X, c1.y, th1, t=cfg.probes, k=cfg.rank, seed=3, max_iter=cfg.max_iter,
+                                    tol=1e-12, pivots=piv)
+    t1 = time.perf_counter()
+    tg, r = gpu_time(lambda: gp.mll_and_grad(k1, X1, y1, probes=cfg.probes, rank=cfg.rank,
+                                             max_iter=cfg.max_iter, tol=0.0, seed=3, precision="bf16x3"))
+    ops.append({"op": "BBMM mll + gradient estimate (pivoted Cholesky, probes, mBCG, SLQ, gradient)", "n": n1,
+                "probes": cfg.probes, "rank": cfg.rank, "iterations": cfg.max_iter, "cpu_s": t1 - t0, "gpu_s": tg,
+                "gpu_over_cpu_speed": (t1 - t0) / tg, "mll_rel_diff": abs(r.mll - o["mll"]) / abs(o["mll"])})
+    for op in ops:
+        op["cores"] = blas or 1
+        log(f"cpu vs gpu: {op['op']} n={op['n']}: cpu {op['cpu_s']:.2f} s, gpu {op['gpu_s'] * 1e3:.2f} ms")
+    return cpu, acc, ops
 
 
 def protocol_leg(gp, synth, torch, dev, np, q, steps=30):
