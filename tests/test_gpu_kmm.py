@@ -162,3 +162,35 @@ def test_fp64_cross_product_matches_oracle(m):
     scale = ok.cross_matmul(Z, X, th, np.abs(V).T).T
     err = np.max(np.abs(got - ref) / scale)
     assert err <= 1e-13
+
+
+MID_CASES = [
+    # n, d, t, kind: mid-size square products, ragged tails, every instantiated K-step class
+    (32768, 48, 16, ok.MATERN52),
+    (40000 + 37, 48, 9, ok.MATERN52),   # ragged last chunk and last 256-row workgroup
+    (40000 + 37, 32, 1, ok.RBF),        # a single column, the other kernel, 4 K steps
+    (50001, 7, 16, ok.MATERN52),        # 2 K steps
+]
+
+
+@pytest.mark.parametrize("n,d,t,kind", MID_CASES)
+def test_mid_size_square_products_match_oracle(n, d, t, kind):
+    """Rows at every 768th boundary, the first and last rows and random rows against the oracle; two
+    runs bitwise identical."""
+    X, th, V = _case(n, d, t, True, seed=5, kind=kind)
+    band = 768
+    edges = [r for b in range(band, n, band) for r in (b - 1, b, b + 1)]
+    rows = np.unique(np.concatenate([np.random.default_rng(1).choice(n, 64, replace=False), edges[:60],
+                                     [0, 1, 255, 256, n - 2, n - 1]]))
+    rows = rows[rows < n]
+    got = _run(th, X, V, "bf16x3")
+    ref = ok.khat_matmul(X, th, V.T, rows=rows).T
+    err = col_rel_err(got[:, rows], ref)
+    diag = (th.sf + th.noise) * V[:, rows]
+    err_off = col_rel_err(got[:, rows] - diag, ref - diag)
+    again = _run(th, X, V, "bf16x3")
+    print(f"square n={n} d={d} t={t} kind={kind}: err={err:.3e} off={err_off:.3e} rows={rows.size}",
+          file=sys.stderr, flush=True)
+    assert err <= TOL["bf16x3"]
+    assert err_off <= TOL_OFF["bf16x3"]
+    np.testing.assert_array_equal(got, again)
