@@ -134,6 +134,10 @@ FP64_CASES = [
     (1000, 64, 20, True),        # widest features of the form, two column groups
     (1, 5, 1, True),
     (2048, 32, 9, False),
+    (1500 + 3, 48, 50, True),    # block CG width: four column groups, one per wave
+    (777, 32, 40, True),         # three column groups (one wave idle in the product)
+    (500, 64, 64, False),        # the widest single pass
+    (300 + 1, 16, 70, True),     # two passes over the columns
 ]
 
 
