@@ -388,8 +388,9 @@ def fit_c4(args, synth, torch, dev, np):
 
 def noise_sweep(gp, _lib, synth, torch, dev, np):
     """Where each product precision stops resolving K_hat (Sec. 3.2: rounding beyond the noise breaks
-    the solver).  Two n = 16,384 data sets: the ill-conditioned variant of the n = 65,536 workload's
-    layout, and the same layout with nearly repeated pairs of rows (lambda_min(K) ~ 1e-5)."""
+    the solver), and AltBBMM (FP64 block CG, Nystrom rank 1024) beside mBCG.  Two n = 16,384 data sets:
+    the ill-conditioned variant of the n = 65,536 workload's layout, and the same layout with nearly
+    repeated pairs of rows (lambda_min(K) ~ 1e-5)."""
     n, t, rank, tol, max_iter = 16384, 15, 100, 1e-6, 1500
     out = {"n": n, "probes": t, "rank": rank, "tol": tol, "max_iter": max_iter, "runs": []}
     p = synth.make_problem("c2", n=n, cond_variant=True)
@@ -422,6 +423,30 @@ def noise_sweep(gp, _lib, synth, torch, dev, np):
                 out["runs"].append(rec)
                 log(f"noise {label} {noise:.0e} {prec}: {rec['status']} {rec['iters']} it, y: recurrence "
                     f"{r.relres[0]:.1e} true {true:.1e}, {dt:.2f} s")
+            # AltBBMM: FP64 block CG on [y | 15 probes] with the rank-1024 Nystrom preconditioner
+            rec = {"data": label, "noise": noise, "precision": "fp64", "solver": "altbbmm"}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                M = np.sort(np.random.default_rng(np.random.SeedSequence([17, 12])).choice(n, 1024, replace=False))
+                ny = gp.nystrom_precond(k, X, M)
+                Bb = torch.cat([y[None, :], torch.from_numpy(synth.random_block(n, t, 11)).to(dev)])
+                r = gp.bcg(k, X, Bb, max_iter, tol, pc=ny, precision="fp64")
+            except _lib.GpError as e:
+                rec.update(status="breakdown", error=str(e), seconds=time.perf_counter() - t0)
+                out["runs"].append(rec)
+                log(f"noise {label} {noise:.0e} altbbmm fp64: breakdown ({e})")
+            else:
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                KU = gp.kmm(k, X, r.W[:1].contiguous(), precision="fp64")
+                true = float(torch.linalg.norm(KU[0] - y) / torch.linalg.norm(y))
+                rec.update(status="converged" if r.status == 0 else "max_iter", iters=int(r.iters),
+                           relres_max=float(r.relres.max()), true_relres_y=true, seconds=dt, kept=ny.kept)
+                out["runs"].append(rec)
+                log(f"noise {label} {noise:.0e} altbbmm fp64: {rec['status']} {r.iters} it, y true {true:.1e}, "
+                    f"{dt:.2f} s (Nystrom kept {ny.kept})")
+                del ny, Bb, r
             del pc, B
         del X, y
         torch.cuda.empty_cache()
