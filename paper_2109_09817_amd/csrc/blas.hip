@@ -317,19 +317,25 @@ __global__ void bidiag_solve_kernel(double* __restrict__ QR, int64_t n, int K, c
   }
 }
 
-// mean[q] = P[q]; var[q] = s_f - sum_{c=1..kc} P[c*m + q]^2 (fixed order per row).
-__global__ void predict_finish_kernel(const double* __restrict__ P, int64_t m, int kc, double sf,
-                                      double* __restrict__ mean, double* __restrict__ var) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  mean[q] = P[q];
+// mean[q] = P[q]; var[q] = s_f - sum_{c=1..kc} P[c*m + q]^2.  One wave per
+// query row: lane l adds the columns 1 + l, 65 + l, ... in order, then an XOR
+// butterfly adds the lanes (the same order on every lane, fixed by kc alone).
+__global__ __launch_bounds__(256) void predict_finish_kernel(const double* __restrict__ P, int64_t m, int kc,
+                                                             double sf, double* __restrict__ mean,
+                                                             double* __restrict__ var) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= m) return;  // whole wave
+  if (lane == 0) mean[q] = P[q];
   if (var) {
     double s = 0.0;
-    for (int c = 1; c <= kc; ++c) {
+    for (int c = 1 + lane; c <= kc; c += 64) {
       const double v = P[(int64_t)c * m + q];
       s += v * v;
     }
-    var[q] = sf - s;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) var[q] = sf - s;
   }
 }
 
@@ -561,7 +567,7 @@ hipError_t launch_bidiag_solve(double* QR, int64_t n, int K, const double* lm, h
 
 hipError_t launch_predict_finish(const double* P, int64_t m, int kc, double sf, double* mean, double* var,
                                  hipStream_t st) {
-  predict_finish_kernel<<<blocks_for(m), kThreads, 0, st>>>(P, m, kc, sf, mean, var);
+  predict_finish_kernel<<<(unsigned)((m + 3) / 4), 256, 0, st>>>(P, m, kc, sf, mean, var);
   return hipGetLastError();
 }
 

@@ -397,6 +397,182 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ wide cross sweep
+//
+// The prediction product K(Z, X) [alpha | R] has few query rows (a request
+// batch) and many columns (1 + k_c).  The sweep above evaluates each kernel
+// entry once per 64-column group; here a workgroup owns 64 query rows and all
+// columns of one chunk split.  Per 32-point chunk, wave w evaluates the
+// distances and the profile of row block w (16 rows) into an LDS tile (BF16
+// hi / lo, two buffers so that one barrier per chunk suffices); then every
+// wave multiplies the four row blocks' tiles by its own column blocks (cb = w,
+// w + 4, ...).  Both operand streams run one chunk ahead in registers: the
+// point fragments of chunk c + 1 are loaded during chunk c - 1 and written to
+// LDS at the top of chunk c, and each wave's V fragments of chunk c + 1 are
+// loaded during chunk c.  FP32 windows of kFlush chunks are added into the
+// split's FP64 partials (this workgroup owns those slots) in the same order
+// as the sweep above, so each output row's sums depend on n only, not on the
+// batch.  Workgroups are numbered so that the row groups of one split run
+// back to back on one XCD and share the chunk data in its L2.
+constexpr int kWideNB = 5;  // column blocks per wave: 4 waves x 5 x 16 = 320 >= 1 + 256 columns
+
+struct WideArgs {
+  const void* xr;  // b stream (training points)
+  const void* xc;  // query-row fragments
+  const void* vf;  // V fragments, vstride 16-column blocks per chunk
+  double* part;    // [split][tpad][mpad]
+  int64_t mpad, nchunks, cps, nsplit;
+  int ntb, vstride, tpad, rgroups;
+};
+
+template <int KS, int KIND>
+__global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
+  constexpr int kPoint = 2 * KS * 64;         // 16-byte units of one chunk's point fragments
+  constexpr int kPer = (kPoint + 255) / 256;  // units per thread
+  __shared__ bf16x8 stage[2][kPoint];
+  __shared__ bf16x8 tile[2][4][2][64];  // [parity][row block][hi / lo][lane]
+  // hardware workgroup i runs on XCD i % 8; the j-th workgroup an XCD receives
+  // (j = i / 8) takes row group j % R of split 8 (j / R) + i % 8
+  const int64_t hw = blockIdx.x;
+  const int64_t j8 = hw >> 3;
+  const int rg = (int)(j8 % a.rgroups);
+  const int64_t split = (j8 / a.rgroups) * 8 + (hw & 7);
+  if (split >= a.nsplit) return;  // whole workgroup, before any barrier
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t ablk = (int64_t)rg * 4 + wave;  // this wave's row block (16 rows)
+  const bf16x8* __restrict__ xr = (const bf16x8*)a.xr;
+  const bf16x8* __restrict__ xc = (const bf16x8*)a.xc;
+  const bf16x8* __restrict__ vf = (const bf16x8*)a.vf;
+  bf16x8 A[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) A[ks] = xc[(ablk * KS + ks) * 64 + lane];
+  f32x4 acc[4][kWideNB];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int jb = 0; jb < kWideNB; ++jb) acc[rb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t c_begin = split * a.cps;
+  const int64_t c_end = c_begin + a.cps < a.nchunks ? c_begin + a.cps : a.nchunks;
+
+  // Loads are unconditional (indexes clamped into the chunk and to the last
+  // column block) so that the number in flight is the same on every path and
+  // the waits before each use cover only what that use needs.
+  bf16x8 pre[kPer];
+  auto fetch = [&](int64_t ch) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int u = tid + 256 * r < kPoint ? tid + 256 * r : kPoint - 1;
+      pre[r] = xr[(2 * ch * KS) * 64 + u];
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int u = tid + 256 * r;
+      if (u < kPoint) stage[buf][u] = pre[r];
+    }
+  };
+  bf16x8 Vc[kWideNB][2], Vn[kWideNB][2];
+  auto vload = [&](int64_t ch, bf16x8(&Vx)[kWideNB][2]) {
+#pragma unroll
+    for (int jb = 0; jb < kWideNB; ++jb) {
+      const int cb = wave + 4 * jb < a.ntb ? wave + 4 * jb : a.ntb - 1;
+      Vx[jb][0] = vf[((ch * a.vstride + cb) * 2 + 0) * 64 + lane];
+      Vx[jb][1] = vf[((ch * a.vstride + cb) * 2 + 1) * 64 + lane];
+    }
+  };
+  // the FP32 window into the split's FP64 partials (written by the first
+  // window); later windows read a column block's 16 partials at once, then add
+  bool first_window = true;
+  auto flush = [&]() {
+    const int64_t row0 = (int64_t)rg * 64 + 4 * (lane >> 4);
+#pragma unroll
+    for (int jb = 0; jb < kWideNB; ++jb) {
+      const int cb = wave + 4 * jb;
+      if (cb < a.ntb) {
+        const int64_t col = (int64_t)cb * 16 + (lane & 15);
+        double* dst = a.part + (split * a.tpad + col) * a.mpad + row0;
+        double old[4][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) old[rb][i] = first_window ? 0.0 : dst[16 * rb + i];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dst[16 * rb + i] = old[rb][i] + (double)acc[rb][jb][i];
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    first_window = false;
+  };
+
+  fetch(c_begin);
+  stash(0);
+  if (c_begin + 1 < c_end) fetch(c_begin + 1);
+  vload(c_begin, Vc);
+  // drain the prologue's loads: the loop then starts with nothing in flight,
+  // as it does after every iteration (the V copy below waits for the loads
+  // issued at its top), so no wait inside the loop covers a newer load
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t ch = c_begin; ch < c_end; ++ch) {
+    const int cur = (int)((ch - c_begin) & 1);
+    const bool more = ch + 1 < c_end;
+    // stage[cur ^ 1] was last read by every wave's phase A of the previous
+    // chunk, which the previous barrier closed
+    if (more) stash(cur ^ 1);
+    if (ch + 2 < c_end) fetch(ch + 2);
+    if (more) vload(ch + 1, Vn);
+    // phase A: this wave's row block against the chunk
+    {
+      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][ks * 64 + lane], A[ks], s0, 0, 0, 0);
+        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][(KS + ks) * 64 + lane], A[ks], s1, 0, 0, 0);
+      }
+      f32x8 mv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mv[i] = profile<KIND, false>(s0[i]);
+        mv[4 + i] = profile<KIND, false>(s1[i]);
+      }
+      bf16x8 H, L;
+      split_bf16x8(mv, H, L);
+      tile[cur][wave][0][lane] = H;
+      tile[cur][wave][1][lane] = L;
+    }
+    // the four tiles of this chunk, and the next chunk's points, are in LDS
+    __syncthreads();
+    // phase B: the four row blocks against this wave's column blocks
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const bf16x8 TH = tile[cur][rb][0][lane];
+      const bf16x8 TL = tile[cur][rb][1][lane];
+#pragma unroll
+      for (int jb = 0; jb < kWideNB; ++jb) {
+        if (wave + 4 * jb < a.ntb) {
+          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TH, Vc[jb][0], acc[rb][jb], 0, 0, 0);
+          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TH, Vc[jb][1], acc[rb][jb], 0, 0, 0);
+          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TL, Vc[jb][0], acc[rb][jb], 0, 0, 0);
+        }
+      }
+    }
+    if (((ch - c_begin + 1) % kFlush) == 0 || !more) flush();
+    if (more) {
+#pragma unroll
+      for (int jb = 0; jb < kWideNB; ++jb) {
+        Vc[jb][0] = Vn[jb][0];
+        Vc[jb][1] = Vn[jb][1];
+      }
+    }
+  }
+}
+
 template <int KQ, int NT, int KIND>
 __global__ __launch_bounds__(256, 2) void sweep_fp32_kernel(SweepArgs a) {
   constexpr int NA = NAOf<NT>::value;
@@ -523,6 +699,27 @@ __global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsp
   out[c * ldo + r] = o;
 }
 
+// The split sum of the wide sweep: a workgroup takes one column and 64 rows,
+// wave k adds the splits k, k + 4, ... in split order, and the four sums are
+// then added in wave order, so the order depends on n alone.
+__global__ __launch_bounds__(256) void wide_epilogue_kernel(const double* __restrict__ part, int64_t nsplit,
+                                                            int tpad, int64_t mpad, int64_t m, double sf,
+                                                            double* __restrict__ out, int64_t ldo) {
+  __shared__ double red[4][64];
+  const int r = threadIdx.x & 63;
+  const int k = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + r;
+  const int64_t c = blockIdx.y;
+  double s = 0.0;
+  if (q < m) {
+#pragma unroll 4
+    for (int64_t sp = k; sp < nsplit; sp += 4) s += part[(sp * tpad + c) * mpad + q];
+  }
+  red[k][r] = s;
+  __syncthreads();
+  if (k == 0 && q < m) out[c * ldo + q] = sf * (((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]);
+}
+
 // ------------------------------------------------------------------ host side
 
 // Optional timing of the tile sweeps: HIP events recorded on the sweep's own
@@ -629,7 +826,7 @@ static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_in
   const int64_t nchunks = npad / 32;
   if (row_independent) {
     // depends on n only: each output row sees the same chunk boundaries whatever m is
-    s.cps = std::max<int64_t>(8, (nchunks + 63) / 64);
+    s.cps = std::max<int64_t>(8, (nchunks + 127) / 128);
   } else {
     const int64_t row_wgs = mpad / (64 * na_of(s.nt)) * s.groups;
     const int64_t want = std::max<int64_t>(1, (2048 + row_wgs - 1) / row_wgs);
@@ -1085,6 +1282,67 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
   return hipGetLastError();
 }
 
+template <int KS>
+static void launch_wide(int kind, dim3 grid, const WideArgs& a, hipStream_t st) {
+  if (kind == GP_MATERN52)
+    wide_cross_bf16x3_kernel<KS, GP_MATERN52><<<grid, 256, 0, st>>>(a);
+  else
+    wide_cross_bf16x3_kernel<KS, GP_RBF><<<grid, 256, 0, st>>>(a);
+}
+
+// Row-independent BF16X3 cross products (prediction): the wide sweep, same splits and partials.
+static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc, const double* Vdiag, int64_t ldv,
+                                 double* out, int64_t ldo, hipStream_t st) {
+  WideArgs a;
+  a.xr = p.xr;
+  a.xc = p.xc;
+  a.vf = p.vf;
+  a.part = p.part;
+  a.mpad = p.mpad;
+  a.nchunks = p.nchunks;
+  a.cps = sc.cps;
+  a.nsplit = sc.nsplit;
+  a.ntb = (t + 15) / 16;
+  a.vstride = sc.groups * sc.nt;  // the V fragments hold whole launch groups
+  a.tpad = a.ntb * 16;
+  a.rgroups = (int)std::max<int64_t>(1, (p.m + 63) / 64);  // live 64-row groups (mpad is a multiple of 256)
+  const dim3 grid((unsigned)(a.rgroups * ((sc.nsplit + 7) / 8 * 8)));
+  SweepTiming::Rec rec{};
+  bool timed = false;
+  {
+    std::lock_guard<std::mutex> g(timing().mu);
+    timed = timing().on;
+  }
+  if (timed) {
+    hipError_t e = hipEventCreate(&rec.a);
+    if (e == hipSuccess) e = hipEventCreate(&rec.b);
+    if (e == hipSuccess) e = hipEventRecord(rec.a, st);
+    if (e != hipSuccess) return e;
+  }
+  switch (p.ks) {
+    case 2: launch_wide<2>(p.kind, grid, a, st); break;
+    case 4: launch_wide<4>(p.kind, grid, a, st); break;
+    case 5: launch_wide<5>(p.kind, grid, a, st); break;
+    case 7: launch_wide<7>(p.kind, grid, a, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (timed) {
+    e = hipEventRecord(rec.b, st);
+    if (e != hipSuccess) return e;
+    rec.flops = 2.0 * (double)p.m * (double)p.n * (double)(p.d + t);
+    rec.n = p.n;
+    rec.m = p.m;
+    rec.t = t;
+    std::lock_guard<std::mutex> g(timing().mu);
+    timing().recs.push_back(rec);
+  }
+  const dim3 egrid((unsigned)((p.m + 63) / 64), (unsigned)t);
+  wide_epilogue_kernel<<<egrid, 256, 0, st>>>(p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf, out, ldo);
+  return hipGetLastError();
+}
+
 hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
                      hipStream_t st, bool row_independent) {
   if (t < 1 || t > p.tmax) return hipErrorInvalidValue;
@@ -1092,6 +1350,8 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   const bool mixed = p.precision == GP_PREC_BF16X3;
   const int ntb = (t + 15) / 16;
   const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
+  if (row_independent && mixed && !p.square && ntb <= 4 * kWideNB && p.ks <= 7)
+    return kmm_sweep_wide(p, t, sc, Vdiag, ldv, out, ldo, st);
   SweepArgs a;
   a.xr = p.xr;
   a.xc = p.xc;

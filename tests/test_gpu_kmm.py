@@ -93,6 +93,24 @@ def test_cross_rows_are_independent_of_the_batch():
     np.testing.assert_array_equal(full[:, 100:137], part)
 
 
+@pytest.mark.parametrize("n,d,t,m,kind", [
+    (150_000, 48, 257, 150, ok.MATERN52),  # the prediction shape: 1 + 256 columns, 3 row groups (ragged)
+    (140_001, 16, 33, 70, ok.RBF),          # 3 column blocks, 2 row groups
+])
+def test_long_split_cross_product_matches_oracle(n, d, t, m, kind):
+    # Chunk splits longer than one FP32 window (the FP64 partials are added to),
+    # the widest column set, and the batch independence at that size.
+    X, th, V = _case(n, d, t, True, seed=11, kind=kind)
+    Z = synth.query_molecule("c2", m, seed=7)[:, :d]
+    got = _run(th, X, V, "bf16x3", Z=Z)
+    ref = ok.cross_matmul(Z, X, th, V.T).T
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"cross n={n} t={t} m={m} err={err:.3e}", file=sys.stderr, flush=True)
+    assert err <= TOL_OFF["bf16x3"]
+    part = _run(th, X, V, "bf16x3", Z=Z[64:80])
+    np.testing.assert_array_equal(got[:, 64:80], part)
+
+
 def test_repeat_runs_are_bitwise_identical():
     n, d, t = 4096, 48, 16
     X, th, V = _case(n, d, t, True, seed=2)
