@@ -301,6 +301,35 @@ def test_predict_model_rows_independent_of_batch():
     np.testing.assert_array_equal(host(v_all)[50:300], host(v_mid))
 
 
+@pytest.mark.parametrize("kc", [0, 256])
+def test_predict_mean_only_and_full_width_cache(kc):
+    # k_c = 0: one column (the mean alone, no variance); k_c = 256: the widest cache,
+    # 257 columns, with a random R so that every column carries weight.
+    import torch
+    from paper_2109_09817_amd import gp
+    n, d, m = 20_011, 48, 97
+    X, y, th = _problem(n, d, True)
+    rng = np.random.default_rng(21)
+    alpha = rng.standard_normal(n)
+    R = rng.standard_normal((kc, n)) * 0.01 if kc else None
+    Z = synth.query_molecule("c2", m, seed=12)[:, :d]
+    mean, var = gp.predict(_gk(th), dev(X), dev(alpha), dev(Z), None if R is None else dev(R))
+    torch.cuda.synchronize()
+    mscale = ok.cross_matmul(Z, X, th, np.abs(alpha))
+    em = np.max(np.abs(host(mean) - ok.cross_matmul(Z, X, th, alpha)) / mscale)
+    log(f"predict k_c={kc}: mean err / |K||alpha| {em:.2e}")
+    assert em <= EPS_PRODUCT["bf16x3"]
+    if kc == 0:
+        assert var is None
+        return
+    vref = cached_variance(Z, X, th, R.T)
+    KRabs = ok.cross_matmul(Z, X, th, np.abs(R).T)
+    vscale = th.sf + np.sum(KRabs * KRabs, axis=1)
+    ev = np.max(np.abs(host(var) - vref) / vscale)
+    log(f"predict k_c={kc}: var err / (s_f + |K||R|^2) {ev:.2e}")
+    assert ev <= 2 * EPS_PRODUCT["bf16x3"]
+
+
 def test_bad_input_is_reported():
     from paper_2109_09817_amd import _lib, gp
     X, y, th = _problem(512, 8, True)
