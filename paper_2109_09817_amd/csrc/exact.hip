@@ -11,10 +11,11 @@
 //
 // with dK/dlog l_j = psi(r) (dx_j / l_j)^2, psi(r) = (5/3) s_f (1 + sqrt5 r)
 // e^{-sqrt5 r} (Matern-5/2; RBF: k), dK/dlog s_f = K and dK_hat/dlog sigma^2
-// = sigma^2 I.  Every O(n^3) step is a sequence of 64 x 64 x 64 FP64 tile
-// products C -= P Q (or C = P Q), the panels staged in LDS; triangular solves
-// against a 64 x 64 diagonal block multiply by its inverse (formed in LDS by
-// one workgroup), so that they are tile products too.
+// = sigma^2 I.  Every O(n^3) step is a sequence of 64 x 64 FP64 tile
+// products C -= P Q (or C = P Q) over k <= 256 on the FP64 matrix cores, the
+// panels staged in LDS; triangular solves against a 64 x 64 diagonal block
+// multiply by its inverse (formed in LDS by one workgroup), so that they are
+// tile products too.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -83,31 +84,44 @@ __global__ __launch_bounds__(256) void form_khat_kernel(const double* __restrict
 // Load the factored diagonal block L[i0.., i0..] (ib rows) into LDS, identity-padded.
 __device__ __forceinline__ void load_diag_block(const double* __restrict__ L, int64_t n, int64_t i0, int ib,
                                                 double (*Ls)[kEb + 1]) {
-  for (int e = threadIdx.x; e < kEb * kEb; e += blockDim.x) {
-    const int r = e / kEb, c = e % kEb;
-    Ls[r][c] = (r < ib && c < ib) ? (c <= r ? L[(i0 + r) * n + i0 + c] : 0.0) : (r == c ? 1.0 : 0.0);
+  constexpr int kPer = kEb * kEb / 256;  // 256 threads
+  double v[kPer];  // every load in flight before the first LDS write
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int e = (int)threadIdx.x + 256 * it, r = e / kEb, c = e % kEb;
+    v[it] = (r < ib && c < ib) ? (c <= r ? L[(i0 + r) * n + i0 + c] : 0.0) : (r == c ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int e = (int)threadIdx.x + 256 * it;
+    Ls[e / kEb][e % kEb] = v[it];
   }
 }
 
-// Xs = Ls^{-1} for a lower-triangular 64 x 64 Ls in LDS, 256 threads: lanes
-// 4j..4j+3 form column j by forward substitution against e_j, lane s summing
-// the terms m = s (mod 4) and keeping in Xs only the entries of its own class,
-// so that each lane reads back what it wrote; the four partial sums meet by
-// shuffles.  Ends with a barrier; Xs is complete (zero above the diagonal).
+// Xs = Ls^{-1} for a lower-triangular 64 x 64 Ls in LDS (zero above the
+// diagonal), 256 threads: lanes 4j..4j+3 form column j by forward
+// substitution against e_j, lane s keeping in registers the entries
+// X[4q + s][j] of its residue class and summing their terms.  Entries not yet
+// formed (and those above the diagonal) are zero, so every row takes the same
+// 16 terms per lane and no index test; the four partial sums meet by shuffles.
+// Ends with a barrier; Xs is complete (zero above the diagonal).
 __device__ __forceinline__ void diag_inverse(const double (*Ls)[kEb + 1], double (*Xs)[kEb + 1]) {
   const int j = threadIdx.x >> 2, sub = threadIdx.x & 3;
+  double x[kEb / 4];
+#pragma unroll
+  for (int q = 0; q < kEb / 4; ++q) x[q] = 0.0;
+#pragma unroll
   for (int r = 0; r < kEb; ++r) {
-    if (r < j) {
-      if ((r & 3) == sub) Xs[r][j] = 0.0;
-      continue;  // uniform over the four lanes of column j
-    }
     double part = 0.0;
-    for (int m = j + ((sub - j) & 3); m < r; m += 4) part = fma(Ls[r][m], Xs[m][j], part);
+#pragma unroll
+    for (int q = 0; q < kEb / 4; ++q) part = fma(Ls[r][4 * q + sub], x[q], part);
     part += __shfl_xor(part, 1);
     part += __shfl_xor(part, 2);
-    const double x = ((r == j ? 1.0 : 0.0) - part) / Ls[r][r];
-    if ((r & 3) == sub) Xs[r][j] = x;
+    const double xr = ((r == j ? 1.0 : 0.0) - part) / Ls[r][r];
+    if ((r & 3) == sub) x[r >> 2] = xr;
   }
+#pragma unroll
+  for (int q = 0; q < kEb / 4; ++q) Xs[4 * q + sub][j] = x[q];
   __syncthreads();
 }
 
@@ -121,9 +135,19 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
                                                          int* __restrict__ info, double* __restrict__ Dinv) {
   __shared__ double Ls[kEb][kEb + 1];
   __shared__ double Xs[kEb][kEb + 1];
-  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-    const int r = e / kEb, c = e % kEb;
-    Ls[r][c] = (r < jb && c < jb) ? A[(j0 + r) * n + j0 + c] : (r == c ? 1.0 : 0.0);
+  {
+    constexpr int kPer = kEb * kEb / 256;
+    double v[kPer];  // every load in flight before the first LDS write
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it, r = e / kEb, c = e % kEb;
+      v[it] = (r < jb && c < jb) ? A[(j0 + r) * n + j0 + c] : (r == c ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it;
+      Ls[e / kEb][e % kEb] = v[it];
+    }
   }
   int bad = 0;  // thread 0 only
   for (int k = 0; k < kEb; ++k) {
@@ -137,11 +161,15 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
     if ((int)threadIdx.x > k && (int)threadIdx.x < kEb) Ls[threadIdx.x][k] /= piv;
     __syncthreads();
     if (threadIdx.x == 0) Ls[k][k] = piv;
+    // thread (wave w, lane c) updates entry c of the rows w + 4 it; every read
+    // is issued unconditionally so that they overlap, the write is guarded
+    const int c = threadIdx.x & (kEb - 1), w = threadIdx.x >> 6;
+    const double lck = Ls[c][k];
 #pragma unroll
-    for (int it = 0; it < kEb * kEb / 256; ++it) {
-      const int e = threadIdx.x + 256 * it;
-      const int r = e / kEb, c = e % kEb;
-      if (c > k && c <= r) Ls[r][c] -= Ls[r][k] * Ls[c][k];
+    for (int it = 0; it < kEb / 4; ++it) {
+      const int r = w + 4 * it;
+      const double v = Ls[r][c] - Ls[r][k] * lck;
+      if (c > k && c <= r) Ls[r][c] = v;
     }
   }
   __syncthreads();
@@ -173,25 +201,44 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* __restr
 // ---------------------------------------------------------------- tile updates
 
 // C[R + r][Cc + c] -= sum_{k < kb} P(r, k) Q(k, c) (ASSIGN: =) over a set of
-// 64 x 64 tiles, with
+// 64 x 64 tiles (k in chunks of 64 staged in LDS in turn), with
 //   P(r, k) = PT ? Pm[(p0 + k) ldp + pr + r] : Pm[(pr + r) ldp + p0 + k]
 //   Q(k, c) = QT ? Qm[(qc + c) ldq + q0 + k] : Qm[(q0 + k) ldq + qc + c]
 // where pr = R (pfix < 0) or pfix, and qc = Cc (qfix < 0) or qfix.  Tile (ti,
 // tj) has R = rbase + 64 ti, Cc = cbase + 64 tj; LOWER enumerates tj <= ti <
 // nrt, otherwise the nrt x nct rectangle.  Output rows and columns at or beyond
-// n are skipped (their operands read as 0).  Every operand is staged in LDS
-// before the tile is written, so C's tile may be one of the operand tiles
-// (never another workgroup's).  Each thread owns a 4 x 4 block (rows 4 tr + i,
-// columns 4 tc + j), so that its operands are two 16-byte LDS reads per side.
+// n are skipped (their operands read as 0).  Every operand is read before
+// the tile is written, so C's tile may be one of the operand tiles (never
+// another workgroup's).  The products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: lane l supplies P(row l % 16, k l / 16) and Q(k l / 16,
+// column l % 16) and receives rows l / 16 + 4 i of column l % 16); wave w
+// owns the 32 x 32 quadrant (w / 2, w % 2).  Each operand keeps in LDS the
+// orientation of its source rows, so that a wave's staging writes are
+// contiguous: k-major [k][x] (pitch 80 doubles) when the source runs along x,
+// x-major [x][k] (pitch 66) when it runs along k.  Both pitches put the 32
+// lanes of a half-wave on distinct banks for the operand reads.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kKMajorLd = kEb + 16;
+constexpr int kXMajorLd = kEb + 2;
+
+template <bool KMAJOR>
+__device__ __forceinline__ int lds_at(int k, int x) {
+  return KMAJOR ? k * kKMajorLd + x : x * kXMajorLd + k;
+}
+
 template <bool PT, bool QT, bool LOWER, bool ASSIGN>
 __global__ __launch_bounds__(256) void tile_update_kernel(const double* Pm, int64_t ldp, int64_t pfix, int64_t p0,
                                                           const double* Qm, int64_t ldq, int64_t qfix, int64_t q0,
                                                           double* Cm, int64_t n, int kb, int64_t rbase, int64_t cbase,
                                                           int nrt, int nct) {
-  __shared__ double Ps[kEb][kEb];  // [k][r]
-  __shared__ double Qs[kEb][kEb];  // [k][c]
+  __shared__ double Ps[kEb * kKMajorLd];  // P(r, k) at lds_at<PT>(k, r)
+  __shared__ double Qs[kEb * kKMajorLd];  // Q(k, c) at lds_at<!QT>(k, c)
   int64_t ti, tj;
-  const int64_t b = blockIdx.x;
+  // Workgroup h runs on XCD h % 8; each XCD takes a contiguous run of tiles
+  // (consecutive tiles of a tile row share their P panel in that XCD's L2).
+  const int64_t T = LOWER ? (int64_t)nrt * (nrt + 1) / 2 : (int64_t)nrt * nct;
+  const int64_t h = blockIdx.x, xcd = h & 7, q8 = T >> 3, rem8 = T & 7;
+  const int64_t b = xcd * q8 + (xcd < rem8 ? xcd : rem8) + (h >> 3);
   if (LOWER) {
     ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
@@ -203,62 +250,82 @@ __global__ __launch_bounds__(256) void tile_update_kernel(const double* Pm, int6
   }
   const int64_t R = rbase + kEb * ti, Cc = cbase + kEb * tj;
   const int64_t pr = pfix < 0 ? R : pfix, qc = qfix < 0 ? Cc : qfix;
-  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-    int r, k;
-    if (PT) {
-      k = e / kEb;
-      r = e % kEb;  // consecutive threads: consecutive columns of row p0 + k
-    } else {
-      r = e / kEb;
-      k = e % kEb;  // consecutive threads: consecutive columns of row pr + r
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = 32 * (wave >> 1), c0 = 32 * (wave & 1);
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // Each thread stages 16 elements of each operand per 64-wide k chunk; the
+  // loads of chunk c + 1 are in flight while chunk c is multiplied.
+  constexpr int kPer = kEb * kEb / 256;
+  double pv[kPer], qv[kPer];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it;
+      const int x = e / kEb, y = e % kEb;  // consecutive threads: consecutive y
+      {
+        const int r = PT ? y : x, k = PT ? x : y;
+        const bool ok = kc + k < kb && R + r < n;
+        const int64_t kk = p0 + kc + k;
+        pv[it] = ok ? (PT ? Pm[kk * ldp + pr + r] : Pm[(pr + r) * ldp + kk]) : 0.0;
+      }
+      {
+        const int c = QT ? x : y, k = QT ? y : x;
+        const bool ok = kc + k < kb && Cc + c < n;
+        const int64_t kk = q0 + kc + k;
+        qv[it] = ok ? (QT ? Qm[(qc + c) * ldq + kk] : Qm[kk * ldq + qc + c]) : 0.0;
+      }
     }
-    const bool ok = k < kb && R + r < n;
-    Ps[k][r] = ok ? (PT ? Pm[(p0 + k) * ldp + pr + r] : Pm[(pr + r) * ldp + p0 + k]) : 0.0;
-  }
-  for (int e = threadIdx.x; e < kEb * kEb; e += 256) {
-    int c, k;
-    if (QT) {
-      c = e / kEb;
-      k = e % kEb;
-    } else {
-      k = e / kEb;
-      c = e % kEb;
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it;
+      const int x = e / kEb, y = e % kEb;
+      Ps[PT ? lds_at<true>(x, y) : lds_at<false>(y, x)] = pv[it];
+      Qs[QT ? lds_at<false>(y, x) : lds_at<true>(x, y)] = qv[it];
     }
-    const bool ok = k < kb && Cc + c < n;
-    Qs[k][c] = ok ? (QT ? Qm[(qc + c) * ldq + q0 + k] : Qm[(q0 + k) * ldq + qc + c]) : 0.0;
-  }
-  __syncthreads();
-  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k = 0; k < kEb; ++k) {
-    double a[4], q[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = Ps[k][4 * tr + i];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) q[j] = Qs[k][4 * tc + j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], q[j], acc[i][j]);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = R + 4 * tr + i;
-    if (row >= n) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = Cc + 4 * tc + j;
-      if (col >= n) continue;
-      if (ASSIGN)
-        Cm[row * n + col] = acc[i][j];
-      else
-        Cm[row * n + col] -= acc[i][j];
+  };
+  load(0);
+  for (int kc = 0; kc < kb; kc += kEb) {
+    if (kc > 0) __syncthreads();  // every wave is done with the previous chunk
+    store();
+    __syncthreads();
+    if (kc + kEb < kb) load(kc + kEb);
+#pragma unroll 4
+    for (int k = 0; k < kEb; k += 4) {
+      const double a0 = Ps[lds_at<PT>(k + lk, r0 + lr)], a1 = Ps[lds_at<PT>(k + lk, r0 + 16 + lr)];
+      const double q0v = Qs[lds_at<!QT>(k + lk, c0 + lr)], q1v = Qs[lds_at<!QT>(k + lk, c0 + 16 + lr)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, q0v, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, q1v, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, q0v, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, q1v, acc[1][1], 0, 0, 0);
     }
   }
+  // the subtracting form reads all 16 of its C entries before writing any
+  double old[2][2][4];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = R + r0 + 16 * rb + lk + 4 * i, col = Cc + c0 + 16 * cb + lr;
+        old[rb][cb][i] = (!ASSIGN && row < n && col < n) ? Cm[row * n + col] : 0.0;
+      }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = R + r0 + 16 * rb + lk + 4 * i, col = Cc + c0 + 16 * cb + lr;
+        if (row < n && col < n) Cm[row * n + col] = ASSIGN ? acc[rb][cb][i] : old[rb][cb][i] - acc[rb][cb][i];
+      }
 }
 
 template <bool PT, bool QT, bool LOWER, bool ASSIGN>
@@ -275,23 +342,47 @@ static hipError_t tile_update(const double* Pm, int64_t ldp, int64_t pfix, int64
 static int ntiles(int64_t len) { return (int)((len + kEb - 1) / kEb); }
 
 // A = L L^T in place (lower triangle; the diagonal blocks' upper parts are
-// zeroed, the rest of the upper triangle is left as it was).
+// zeroed, the rest of the upper triangle is left as it was).  Two levels of
+// blocking: 64-wide panels inside 256-wide super-panels.  A panel updates only
+// the columns of its own super-panel; the trailing matrix beyond it takes the
+// whole super-panel at once (k = 256), so that it is read and written once per
+// 256 columns instead of once per 64.
+constexpr int kSp = 4 * kEb;
+
 static hipError_t cholesky(double* A, int64_t n, int* info, double* Dinv, hipStream_t st) {
-  for (int64_t j0 = 0; j0 < n; j0 += kEb) {
-    const int jb = (int)std::min<int64_t>(kEb, n - j0);
-    const int64_t rest = n - j0 - jb;
-    potrf_diag_kernel<<<1, 256, 0, st>>>(A, n, j0, jb, info, rest > 0 ? Dinv : nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (rest <= 0) break;
-    // L21 = A21 L11^{-T} = A21 Dinv^T (jb = 64 here: only the last block is narrower)
-    e = tile_update<false, true, false, true>(A, n, -1, j0, Dinv, kEb, 0, 0, A, n, jb, j0 + jb, j0, ntiles(rest), 1,
-                                              st);
-    if (e != hipSuccess) return e;
-    // A22 -= L21 L21^T over the lower tiles of the trailing matrix
-    e = tile_update<false, true, true, false>(A, n, -1, j0, A, n, -1, j0, A, n, jb, j0 + jb, j0 + jb, ntiles(rest),
-                                              0, st);
-    if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  for (int64_t J0 = 0; J0 < n; J0 += kSp) {
+    const int64_t Jend = std::min<int64_t>(n, J0 + kSp);
+    for (int64_t j0 = J0; j0 < Jend; j0 += kEb) {
+      const int jb = (int)std::min<int64_t>(kEb, n - j0);
+      const int64_t rest = n - j0 - jb;
+      potrf_diag_kernel<<<1, 256, 0, st>>>(A, n, j0, jb, info, rest > 0 ? Dinv : nullptr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (rest <= 0) return hipSuccess;
+      // L21 = A21 L11^{-T} = A21 Dinv^T for every row below (jb = 64 here)
+      e = tile_update<false, true, false, true>(A, n, -1, j0, Dinv, kEb, 0, 0, A, n, jb, j0 + jb, j0, ntiles(rest),
+                                                1, st);
+      if (e != hipSuccess) return e;
+      // the rest of this super-panel's columns, [j0 + 64, Jend): the lower
+      // triangle of its diagonal part, then the rows below the super-panel
+      const int64_t wcols = Jend - j0 - jb;
+      if (wcols > 0) {
+        e = tile_update<false, true, true, false>(A, n, -1, j0, A, n, -1, j0, A, n, jb, j0 + jb, j0 + jb,
+                                                  ntiles(wcols), 0, st);
+        if (e != hipSuccess) return e;
+        if (n > Jend) {
+          e = tile_update<false, true, false, false>(A, n, -1, j0, A, n, -1, j0, A, n, jb, Jend, j0 + jb,
+                                                     ntiles(n - Jend), ntiles(wcols), st);
+          if (e != hipSuccess) return e;
+        }
+      }
+    }
+    // A22 -= L21 L21^T over the lower tiles beyond the super-panel, k = Jend - J0
+    if (n > Jend) {
+      e = tile_update<false, true, true, false>(A, n, -1, J0, A, n, -1, J0, A, n, (int)(Jend - J0), Jend, Jend,
+                                                ntiles(n - Jend), 0, st);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -306,7 +397,9 @@ __global__ void identity_kernel(double* __restrict__ B, int64_t n) {
 
 // B <- K_hat^{-1} from the Cholesky factor in L: first L^{-1} (lower
 // triangular, so block row i needs columns [0, i0 + 64) only), then
-// L^{-T} L^{-1} on the lower triangle, then mirrored.
+// L^{-T} L^{-1} on the lower triangle, then mirrored.  Both passes are blocked
+// like the factorisation: 64-row blocks update the rest of their 256-row
+// super-block, and the rows beyond it take the whole super-block at once.
 static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st) {
   identity_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(B, n);
   hipError_t e = hipGetLastError();
@@ -315,34 +408,62 @@ static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv
   const int64_t nb = (n + kEb - 1) / kEb;
   trtri_blocks_kernel<<<(unsigned)nb, 256, 0, st>>>(L, n, Dinv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // forward, right-looking: X_i = L_ii^{-1} B_i on columns [0, i0 + ib); then
-  // B_below -= L_below,i X_i on the same columns
-  for (int64_t bi = 0; bi < nb; ++bi) {
-    const int64_t i0 = bi * kEb;
-    const int ib = (int)std::min<int64_t>(kEb, n - i0);
-    const int64_t ncols = i0 + ib;
-    e = tile_update<false, false, false, true>(Dinv + bi * kEb * kEb, kEb, 0, 0, B, n, -1, i0, B, n, ib, i0, 0, 1,
-                                               ntiles(ncols), st);
-    if (e != hipSuccess) return e;
-    const int64_t below = n - i0 - ib;
-    if (below > 0) {
-      e = tile_update<false, false, false, false>(L, n, -1, i0, B, n, -1, i0, B, n, ib, i0 + ib, 0, ntiles(below),
-                                                  ntiles(ncols), st);
+  // forward: X_i = L_ii^{-1} B_i on columns [0, i0 + ib); then B_r -= L_ri X_i
+  // on the same columns for the rows r of the super-block below block i; after
+  // the super-block, the rows below it at once (k = its height, columns
+  // [0, Iend), where X is zero beyond each block's own columns)
+  for (int64_t I0 = 0; I0 < n; I0 += kSp) {
+    const int64_t Iend = std::min<int64_t>(n, I0 + kSp);
+    for (int64_t i0 = I0; i0 < Iend; i0 += kEb) {
+      const int64_t bi = i0 / kEb;
+      const int ib = (int)std::min<int64_t>(kEb, n - i0);
+      const int64_t ncols = i0 + ib;
+      e = tile_update<false, false, false, true>(Dinv + bi * kEb * kEb, kEb, 0, 0, B, n, -1, i0, B, n, ib, i0, 0, 1,
+                                                 ntiles(ncols), st);
+      if (e != hipSuccess) return e;
+      const int64_t below = Iend - i0 - ib;
+      if (below > 0) {
+        e = tile_update<false, false, false, false>(L, n, -1, i0, B, n, -1, i0, B, n, ib, i0 + ib, 0, ntiles(below),
+                                                    ntiles(ncols), st);
+        if (e != hipSuccess) return e;
+      }
+    }
+    if (n > Iend) {
+      e = tile_update<false, false, false, false>(L, n, -1, I0, B, n, -1, I0, B, n, (int)(Iend - I0), Iend, 0,
+                                                  ntiles(n - Iend), ntiles(Iend), st);
       if (e != hipSuccess) return e;
     }
   }
-  // backward, right-looking from the last block: Z_i = L_ii^{-T} C_i on
-  // columns [0, i0 + ib); then, on the lower tiles above,
-  // C[R][Cc] -= L[i-block][R]^T Z[i-block][Cc]
-  for (int64_t bi = nb - 1; bi >= 0; --bi) {
-    const int64_t i0 = bi * kEb;
-    const int ib = (int)std::min<int64_t>(kEb, n - i0);
-    const int64_t ncols = i0 + ib;
-    e = tile_update<true, false, false, true>(Dinv + bi * kEb * kEb, kEb, 0, 0, B, n, -1, i0, B, n, ib, i0, 0, 1,
-                                              ntiles(ncols), st);
-    if (e != hipSuccess) return e;
-    if (i0 > 0) {
-      e = tile_update<true, false, true, false>(L, n, -1, i0, B, n, -1, i0, B, n, ib, 0, 0, ntiles(i0), 0, st);
+  // backward, from the last block: Z_i = L_ii^{-T} C_i on columns
+  // [0, i0 + ib); then C[R][Cc] -= L[i-block][R]^T Z[i-block][Cc] on the lower
+  // tiles of the super-block's rows above block i (their triangle, then the
+  // columns left of the super-block); after the super-block, the lower tiles
+  // of every row above it at once
+  const int64_t nsb = (n + kSp - 1) / kSp;
+  for (int64_t sb = nsb - 1; sb >= 0; --sb) {
+    const int64_t I0 = sb * kSp;
+    const int64_t Iend = std::min<int64_t>(n, I0 + kSp);
+    for (int64_t bi = (Iend - 1) / kEb; bi >= I0 / kEb; --bi) {
+      const int64_t i0 = bi * kEb;
+      const int ib = (int)std::min<int64_t>(kEb, n - i0);
+      const int64_t ncols = i0 + ib;
+      e = tile_update<true, false, false, true>(Dinv + bi * kEb * kEb, kEb, 0, 0, B, n, -1, i0, B, n, ib, i0, 0, 1,
+                                                ntiles(ncols), st);
+      if (e != hipSuccess) return e;
+      if (i0 > I0) {
+        e = tile_update<true, false, true, false>(L, n, -1, i0, B, n, -1, i0, B, n, ib, I0, I0, ntiles(i0 - I0), 0,
+                                                  st);
+        if (e != hipSuccess) return e;
+        if (I0 > 0) {
+          e = tile_update<true, false, false, false>(L, n, -1, i0, B, n, -1, i0, B, n, ib, I0, 0, ntiles(i0 - I0),
+                                                     ntiles(I0), st);
+          if (e != hipSuccess) return e;
+        }
+      }
+    }
+    if (I0 > 0) {
+      e = tile_update<true, false, true, false>(L, n, -1, I0, B, n, -1, I0, B, n, (int)(Iend - I0), 0, 0,
+                                                ntiles(I0), 0, st);
       if (e != hipSuccess) return e;
     }
   }
