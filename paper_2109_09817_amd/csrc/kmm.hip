@@ -968,16 +968,21 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
 // ------------------------------------------------------------------ FP64 form
 //
 // The low-noise regime (sigma^2 down to 1e-8, Sec. 3.2 and Sec. 4) needs K_hat V
-// to FP64 accuracy.  MI355X's FP64 matrix-core peak equals its FP64 vector peak,
-// so this form runs on the VALU.  A workgroup owns 64 output rows (lane = row,
-// its scaled features in registers) and up to 64 columns; per 32-point chunk of
-// the b stream (staged in LDS with its V values) each kernel entry is evaluated
-// once: wave q takes points 8q..8q+7 (r^2 = n_a + n_b - 2 x_a.x_b and the
-// profile in FP64) into an LDS tile M; then the waves share M V, one 16-column
-// group each when there are more than two groups, otherwise the groups times a
-// split of the 32 points, and the point-split partials are added in wave order
-// at the end (deterministic).  The diagonal entry is exactly s_f (m(0) = 1) and
-// sigma^2 V is added exactly.
+// to FP64 accuracy.  Both contractions run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: lane l supplies A(l % 16, k = l / 16) and B(k = l / 16,
+// l % 16), and holds D(l / 16 + 4 i, l % 16)).  A workgroup owns 64 output rows
+// and up to 64 columns; wave w owns rows 16 w .. 16 w + 15, their scaled
+// features held in registers as the B operand.  Per 32-point chunk of the b
+// stream (scaled points, norms and V values staged in LDS), for each 16-point
+// half: the MFMA gives x_b . x_a with the point along D's rows, so after the
+// profile (r^2 = n_a + n_b - 2 x_a.x_b, then m(r) in FP64) register i of every
+// lane holds the entries of points 4 i .. 4 i + 3 of that half, exactly the A
+// operand of the M V step that contracts over them.  Each entry is evaluated
+// once and never leaves registers; the output tile goes through LDS so that
+// the stores are coalesced.  The diagonal entry is exactly s_f (m(0) = 1) and
+// sigma^2 V is added exactly.  Every row's sums run in the same order whatever
+// the other rows are.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // sc64[f] = feature scale (thread f < d); nrm[p] = |x_p (.) sc|^2 for p < rows.
 __global__ void prep_fp64_kernel(const double* __restrict__ X, int64_t rows, int d, Scale sc,
@@ -1000,114 +1005,129 @@ __global__ __launch_bounds__(256) void sweep_fp64_kernel(const double* __restric
                                                          const double* __restrict__ sc64, const double* __restrict__ V,
                                                          int64_t ldv, int t, double sf, double noise, int square,
                                                          double* __restrict__ out, int64_t ldo) {
-  __shared__ double Bs[kF64Chunk][DP];
+  constexpr int kBLd = DP + 2;           // point rows: the MFMA's 16-lane reads hit distinct banks
+  constexpr int kVLd = kF64Chunk + 2;    // V columns, likewise
+  constexpr int kOLd = kF64Rows + 1;     // output tile columns
+  constexpr int kKs = DP / 4;            // K steps of the distance MFMA
+  constexpr int kStage = kF64Chunk * kBLd + kF64Cols * kVLd;
+  constexpr int kBuf = kStage > kF64Cols * kOLd ? kStage : kF64Cols * kOLd;
+  __shared__ double buf[kBuf];  // the chunk's points [j][f] and V [c][j]; at the end the output tile [c][row]
   __shared__ double Ns[kF64Chunk];
-  __shared__ double Xt[DP][kF64Rows];  // the workgroup's scaled rows, feature-major
-  // V values of the chunk [c][j], then the entries [j][row]; after the sweep the
-  // same array holds the reduction rows [wave][c][row]
-  __shared__ double VM[kF64Cols * kF64Chunk + kF64Chunk * kF64Rows];
-  static_assert(kF64Cols * kF64Chunk + kF64Chunk * kF64Rows >= 4 * 16 * kF64Rows, "reduction rows");
-  double* const Vs = VM;
-  double* const Ms = VM + kF64Cols * kF64Chunk;
+  double* const Bs = buf;
+  double* const Vs = buf + kF64Chunk * kBLd;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
   const int64_t a0 = (int64_t)blockIdx.x * kF64Rows;
-  const int64_t a = a0 + lane;
   const int c0 = blockIdx.y * kF64Cols;
   const int tc = t - c0 < kF64Cols ? t - c0 : kF64Cols;  // columns of this pass
-  const int groups = (tc + 15) / 16;                     // 16-column groups
-  // phase-2 roles: column group grp, points [j0, j0 + jcount) of each chunk
-  const int gsplit = groups > 2 ? 4 : groups;  // groups per wave set
-  const int grp = wave % gsplit;
-  const int parts = 4 / gsplit;                // point splits
-  const int jcount = kF64Chunk / parts;
-  const int pj0 = (wave / gsplit) * jcount;
-  for (int e = tid; e < kF64Rows * DP; e += blockDim.x) {
-    const int r = e / DP, f = e - r * DP;
-    Xt[f][r] = (a0 + r < m && f < d) ? Xa[(a0 + r) * d + f] * sc64[f] : 0.0;
-  }
-  const bool live = a < m;
-  const double naa = live ? na[a] : 0.0;
-  double acc[16];
+  const int ncb = (tc + 15) / 16;                        // 16-column blocks
+  const int64_t arow = a0 + 16 * wave + lr;              // this lane's row in the products
+  double xa[kKs];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (int s = 0; s < kKs; ++s) {
+    const int f = 4 * s + lk;
+    xa[s] = (arow < m && f < d) ? Xa[arow * d + f] * sc64[f] : 0.0;
+  }
+  const double naa = arow < m ? na[arow] : 0.0;
+  // the staging threads' feature scales (the same features in every chunk)
+  static_assert(kF64Chunk * DP % 256 == 0 && kF64Chunk * kF64Cols % 256 == 0, "256 threads");
+  double bs[kF64Chunk * DP / 256];
+#pragma unroll
+  for (int it = 0; it < kF64Chunk * DP / 256; ++it) {
+    const int f = (tid + 256 * it) % DP;
+    bs[it] = f < d ? sc64[f] : 0.0;
+  }
+  f64x4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int64_t b0 = 0; b0 < n; b0 += kF64Chunk) {
-    __syncthreads();
-    for (int e = tid; e < kF64Chunk * DP; e += blockDim.x) {
-      const int j = e / DP, f = e - j * DP;
-      const int64_t b = b0 + j;
-      Bs[j][f] = (b < n && f < d) ? Xb[b * d + f] * sc64[f] : 0.0;
-    }
-    for (int e = tid; e < kF64Chunk; e += blockDim.x) Ns[e] = b0 + e < n ? nb[b0 + e] : 0.0;
-    for (int e = tid; e < kF64Chunk * kF64Cols; e += blockDim.x) {
-      const int c = e / kF64Chunk, j = e - c * kF64Chunk;
-      const int64_t b = b0 + j;
-      Vs[c * kF64Chunk + j] = (b < n && c < tc) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
-    }
-    __syncthreads();
-    // phase 1: entries (row lane, points 8 wave .. 8 wave + 7): one feature of the
-    // row per LDS read, applied to eight points (broadcast reads), eight FMA chains
-    const int jb = 8 * wave;
-    double dot[8];
+    {
+      // every staging load of a thread in flight before its first LDS write
+      constexpr int kBPer = kF64Chunk * DP / 256, kVPer = kF64Chunk * kF64Cols / 256;
+      double bv[kBPer], vv[kVPer];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) dot[q] = 0.0;
-#pragma unroll 2
-    for (int f = 0; f < DP; f += 2) {
-      const double x0 = Xt[f][lane], x1 = Xt[f + 1][lane];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) dot[q] = fma(x1, Bs[jb + q][f + 1], fma(x0, Bs[jb + q][f], dot[q]));
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double S = fmax(naa + Ns[jb + q] - 2.0 * dot[q], 0.0);
-      const int64_t b = b0 + jb + q;
-      double mv;
-      if (b >= n) {
-        mv = 0.0;
-      } else if (square && b == a) {
-        mv = 1.0;
-      } else if constexpr (KIND == GP_MATERN52) {
-        const double u = sqrt(S);
-        mv = fma(u, fma(u, 1.0 / 3.0, 1.0), 1.0) * exp(-u);
-      } else {
-        mv = exp(-0.5 * S);
+      for (int it = 0; it < kBPer; ++it) {
+        const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
+        const int64_t b = b0 + j;
+        bv[it] = (b < n && f < d) ? Xb[b * d + f] : 0.0;
       }
-      Ms[(jb + q) * kF64Rows + lane] = mv;
+#pragma unroll
+      for (int it = 0; it < kVPer; ++it) {
+        const int e = tid + 256 * it, c = e / kF64Chunk, j = e - c * kF64Chunk;
+        const int64_t b = b0 + j;
+        vv[it] = (b < n && c < tc) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
+      }
+      const double nv = (tid < kF64Chunk && b0 + tid < n) ? nb[b0 + tid] : 0.0;
+      __syncthreads();  // the previous chunk's readers are done
+#pragma unroll
+      for (int it = 0; it < kBPer; ++it) {
+        const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
+        Bs[j * kBLd + f] = bv[it] * bs[it];
+      }
+#pragma unroll
+      for (int it = 0; it < kVPer; ++it) {
+        const int e = tid + 256 * it, c = e / kF64Chunk;
+        Vs[c * kVLd + e - c * kF64Chunk] = vv[it];
+      }
+      if (tid < kF64Chunk) Ns[tid] = nv;
     }
     __syncthreads();
-    // phase 2: acc[c] += sum over this wave's points of M[row][j] V[j][16 grp + c]
-    if (grp < groups) {
-      for (int j = pj0; j < pj0 + jcount; ++j) {
-        const double mj = Ms[j * kF64Rows + lane];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = fma(mj, Vs[(16 * grp + c) * kF64Chunk + j], acc[c]);
+    for (int pb = 0; pb < 2; ++pb) {
+      // x_b . x_a: D(point 16 pb + lk + 4 i, row arow)
+      f64x4 dt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < kKs; ++s)
+        dt = __builtin_amdgcn_mfma_f64_16x16x4f64(Bs[(16 * pb + lr) * kBLd + 4 * s + lk], xa[s], dt, 0, 0, 0);
+      double mt[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = 16 * pb + lk + 4 * i;
+        const int64_t b = b0 + j;
+        const double S = fmax(naa + Ns[j] - 2.0 * dt[i], 0.0);
+        double mv;
+        if (b >= n) {
+          mv = 0.0;
+        } else if (square && b == arow) {
+          mv = 1.0;
+        } else if constexpr (KIND == GP_MATERN52) {
+          const double u = sqrt(S);
+          mv = fma(u, fma(u, 1.0 / 3.0, 1.0), 1.0) * exp(-u);
+        } else {
+          mv = exp(-0.5 * S);
+        }
+        mt[i] = mv;
+      }
+      // acc(row, column) += sum over the half's points of M(row, point) V(point, column)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        if (cb < ncb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                mt[i], Vs[(16 * cb + lr) * kVLd + 16 * pb + 4 * i + lk], acc[cb], 0, 0, 0);
+        }
       }
     }
   }
-  // point-split partials of one group are added in wave order
-  if (parts > 1) {
-    __syncthreads();
-    double* const red_all = VM;  // [wave][c][row]
+  // acc[cb][i]: row 16 wave + lk + 4 i, column 16 cb + lr -> LDS tile [column][row]
+  __syncthreads();
+  double* const Os = buf;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) red_all[(wave * 16 + c) * kF64Rows + lane] = acc[c];
-    __syncthreads();
-    if (wave >= gsplit) return;
+  for (int cb = 0; cb < 4; ++cb) {
+    if (cb < ncb) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      double s = 0.0;
-      for (int pp = 0; pp < parts; ++pp) s += red_all[((pp * gsplit + grp) * 16 + c) * kF64Rows + lane];
-      acc[c] = s;
+      for (int i = 0; i < 4; ++i) Os[(16 * cb + lr) * kOLd + 16 * wave + lk + 4 * i] = acc[cb][i];
     }
   }
-  if (!live || grp >= groups) return;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = c0 + 16 * grp + c;
-    if (col < t) {
-      double y = sf * acc[c];
-      if (square) y = fma(noise, V[(int64_t)col * ldv + a], y);
-      out[(int64_t)col * ldo + a] = y;
-    }
+  __syncthreads();
+  const int64_t a = a0 + lane;
+  if (a >= m) return;
+  for (int c = wave; c < tc; c += 4) {
+    double y = sf * Os[c * kOLd + lane];
+    if (square) y = fma(noise, V[(int64_t)(c0 + c) * ldv + a], y);
+    out[(int64_t)(c0 + c) * ldo + a] = y;
   }
 }
 
