@@ -29,7 +29,13 @@ def _run(kern_np, X, V, prec, Z=None):
 def _case(n, d, t, cond, seed, kind=ok.MATERN52):
     p = synth.make_problem("c2", n=n, cond_variant=cond, kind=kind, seed=seed)
     X = p.X[:, :d].copy()
-    ell = p.ell[:d] * (math.sqrt(d / 48.0) if cond else 1.0)
+    ell = p.ell[:d]
+    if d > X.shape[1]:  # beyond the workload's 48 features: more features of the same kind
+        extra = d - X.shape[1]
+        rng = np.random.default_rng(seed + 77)
+        X = np.hstack([X, X[:, :extra] + rng.standard_normal((n, extra))])
+        ell = np.concatenate([ell, rng.uniform(0.5, 2.0, extra) * (math.sqrt(2 * p.cfg.d) if cond else 1.0)])
+    ell = ell * (math.sqrt(d / 48.0) if cond else 1.0)
     th = ok.Theta(ell, 1.3, 1e-3, kind)
     V = synth.random_block(n, t, seed)
     return X, th, V
@@ -44,6 +50,7 @@ CASES = [
     (1000, 48, 33, True),    # three 16-column blocks
     (1500, 48, 50, True),    # four column blocks, padded (the AltBBMM block size s = 50)
     (700, 20, 64, True),     # four full column blocks
+    (900, 64, 16, True),     # the widest features (224 BF16x3 K)
     (600, 48, 100, True),    # two column groups of four blocks
     (1, 5, 1, True),         # degenerate: one point
 ]
@@ -81,6 +88,22 @@ def test_cross_product_matches_oracle(m, prec):
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print(f"cross m={m} prec={prec} err={err:.3e}", file=sys.stderr, flush=True)
     assert err <= TOL_OFF[prec]
+
+
+@pytest.mark.parametrize("d", [7, 32, 64])
+def test_cross_product_every_feature_width(d):
+    # The row-independent cross sweep is instantiated per K step count: d = 7, 32
+    # and 64 take 32, 128 and 224 BF16x3 K (48 and 16 are covered above).
+    n, t, m = 2500, 40, 99
+    X, th, V = _case(n, d, t, True, seed=13)
+    Z = synth.query_molecule("c2", m, seed=21)[:, :d]
+    if Z.shape[1] < d:  # widen the queries like the training rows
+        Z = np.hstack([Z, np.random.default_rng(3).standard_normal((m, d - Z.shape[1]))])
+    got = _run(th, X, V, "bf16x3", Z=Z)
+    ref = ok.cross_matmul(Z, X, th, V.T).T
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"cross d={d} err={err:.3e}", file=sys.stderr, flush=True)
+    assert err <= TOL_OFF["bf16x3"]
 
 
 def test_cross_rows_are_independent_of_the_batch():
