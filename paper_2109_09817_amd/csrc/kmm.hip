@@ -84,15 +84,24 @@ __global__ void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_
   double s = 0.0;
   if (p < n) {
     const double* x = X + p * d;
-    for (int j = 0; j < d; ++j) {
-      const double v = x[j] * sc.s[j];
-      if (mixed) {
-        const double h = bf16_round(v);
-        const double l = bf16_round(v - h);
-        s += h * h + 2.0 * h * l;
-      } else {
-        const double f = (float)v;
-        s += f * f;
+    for (int j0 = 0; j0 < d; j0 += 8) {
+      double v[8];  // eight loads in flight (index clamped into the row); the sum keeps its order
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q < d ? j0 + q : d - 1;
+        v[q] = x[j] * sc.s[j];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (j0 + q >= d) break;
+        if (mixed) {
+          const double h = bf16_round(v[q]);
+          const double l = bf16_round(v[q] - h);
+          s += h * h + 2.0 * h * l;
+        } else {
+          const double f = (float)v[q];
+          s += f * f;
+        }
       }
     }
   }
