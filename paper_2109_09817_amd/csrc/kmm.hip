@@ -29,6 +29,10 @@
 //           FP32 accumulation; M is split the same way for the second product.
 //   FP32:   v_mfma_f32_16x16x4_f32 for both products; the squared norms
 //           initialise the distance accumulator.
+// Row-independent BF16X3 cross products with many columns (prediction) use a
+// variant that evaluates each entry once for all columns (the wide sweep), and
+// the FP64 form (low-noise regime) runs both contractions on
+// v_mfma_f64_16x16x4; both are described where they are defined.
 #include "internal.h"
 #include "mfma_bf16.h"
 
