@@ -810,13 +810,13 @@ int kmm_ksteps(int precision, int d) {
   if (precision == GP_PREC_FP64) return d <= kF64MaxD ? 1 : -1;
   if (precision == GP_PREC_BF16X3) {
     const int need = (3 * d + 6 + 31) / 32;
-    static const int kAvail[] = {2, 4, 5, 7, 10, 13};
+    static const int kAvail[] = {2, 4, 5, 7, 13};  // the instantiated sweeps
     for (int k : kAvail)
       if (k >= need) return k;
     return -1;
   }
   const int need = (d + 15) / 16;
-  static const int kAvail32[] = {1, 2, 3, 4, 6, 8};
+  static const int kAvail32[] = {1, 2, 3, 4, 8};  // the instantiated sweeps
   for (int k : kAvail32)
     if (k >= need) return k;
   return -1;

@@ -33,7 +33,7 @@ def _case(n, d, t, cond, seed, kind=ok.MATERN52):
     if d > X.shape[1]:  # beyond the workload's 48 features: more features of the same kind
         extra = d - X.shape[1]
         rng = np.random.default_rng(seed + 77)
-        X = np.hstack([X, X[:, :extra] + rng.standard_normal((n, extra))])
+        X = np.hstack([X, X[:, np.arange(extra) % X.shape[1]] + rng.standard_normal((n, extra))])
         ell = np.concatenate([ell, rng.uniform(0.5, 2.0, extra) * (math.sqrt(2 * p.cfg.d) if cond else 1.0)])
     ell = ell * (math.sqrt(d / 48.0) if cond else 1.0)
     th = ok.Theta(ell, 1.3, 1e-3, kind)
@@ -104,6 +104,24 @@ def test_cross_product_every_feature_width(d):
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print(f"cross d={d} err={err:.3e}", file=sys.stderr, flush=True)
     assert err <= TOL_OFF["bf16x3"]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("d", [80, 128])
+def test_products_beyond_the_workload_features(d, prec):
+    # Up to the ABI's 128 features: the square product and a cross product.
+    n, t, m = 1200, 9, 70
+    X, th, V = _case(n, d, t, True, seed=17)
+    got = _run(th, X, V, prec)
+    ref = ok.khat_matmul(X, th, V.T).T
+    err = col_rel_err(got, ref)
+    Z = X[:m] + np.random.default_rng(5).standard_normal((m, d)) * 0.1
+    gotc = _run(th, X, V, prec, Z=Z)
+    refc = ok.cross_matmul(Z, X, th, V.T).T
+    errc = float(np.linalg.norm(gotc - refc) / np.linalg.norm(refc))
+    print(f"d={d} {prec}: square err {err:.3e} cross err {errc:.3e}", file=sys.stderr, flush=True)
+    assert err <= TOL[prec]
+    assert errc <= TOL_OFF[prec]
 
 
 def test_cross_rows_are_independent_of_the_batch():
