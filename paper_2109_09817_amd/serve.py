@@ -117,7 +117,7 @@ class GpuExecutor(Executor):
 class Server:
     """Admission by slot, row cap and memory budget; FIFO order; continuous batching."""
 
-    def __init__(self, executor: Executor, d: int, hbm_budget: int = 2 << 30, poll_s: float = 2e-4,
+    def __init__(self, executor: Executor, d: int, hbm_budget: int = 2 << 30, poll_s: float = 5e-5,
                  clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
         self.d = d
@@ -216,7 +216,8 @@ class Server:
                     if slot not in self.inflight and self.queue:
                         progressed |= self._admit(slot)
                 if not progressed:
-                    self.cv.wait(timeout=self.poll_s)
+                    # poll the running batches; with none, sleep until a request or close() arrives
+                    self.cv.wait(timeout=self.poll_s if self.inflight else None)
 
 
 def latency_summary(results: List[Result], wall_s: float) -> dict:
