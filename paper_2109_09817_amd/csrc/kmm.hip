@@ -261,9 +261,12 @@ struct SweepArgs {
   int square;    // mask the diagonal (square product)
 };
 
-template <int NT>
+// 16-row blocks per wave: each staged b-stream fragment serves NA tiles and
+// each V fragment NA row blocks, as far as the registers allow (two blocks
+// with three or four column blocks fit only up to KS = 5).
+template <int KS, int NT>
 struct NAOf {
-  static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+  static constexpr int value = NT == 1 ? 4 : (NT == 2 || KS <= 5 ? 2 : 1);
 };
 
 // One 32-point chunk of the b stream staged in LDS: the 2 KS point fragments
@@ -278,7 +281,7 @@ struct ChunkUnits {
 
 template <int KS, int NT, int KIND>
 __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
-  constexpr int NA = NAOf<NT>::value;
+  constexpr int NA = NAOf<KS, NT>::value;
   using CU = ChunkUnits<KS, NT>;
   __shared__ bf16x8 stage[2][CU::kAll];
   const int tid = threadIdx.x;
@@ -586,9 +589,15 @@ __global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
   }
 }
 
+// 16-row blocks per wave of the FP32 form.
+template <int NT>
+struct NAOfF32 {
+  static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 2 : 1);
+};
+
 template <int KQ, int NT, int KIND>
 __global__ __launch_bounds__(256, 2) void sweep_fp32_kernel(SweepArgs a) {
-  constexpr int NA = NAOf<NT>::value;
+  constexpr int NA = NAOfF32<NT>::value;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
@@ -824,14 +833,17 @@ int kmm_ksteps(int precision, int d) {
 
 // Column blocks handled per launch (grid.z groups the rest).
 static int nt_launch(int ntb) { return ntb >= 4 ? 4 : ntb; }
-static int na_of(int nt) { return nt == 1 ? 4 : (nt == 2 ? 2 : 1); }
+static int na_of(int ks, int nt, bool mixed) {  // NAOf<KS, NT> of the launched kernel
+  if (!mixed) return nt == 1 ? 4 : (nt == 2 ? 2 : 1);
+  return nt == 1 ? 4 : (nt == 2 || ks <= 5 ? 2 : 1);
+}
 
 struct SplitChoice {
   int nt, groups, tpad;
   int64_t cps, nsplit;
 };
 
-static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_independent) {
+static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_independent, int ks, bool mixed) {
   SplitChoice s;
   s.nt = nt_launch(ntb);
   s.groups = (ntb + s.nt - 1) / s.nt;
@@ -841,7 +853,7 @@ static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_in
     // depends on n only: each output row sees the same chunk boundaries whatever m is
     s.cps = std::max<int64_t>(8, (nchunks + 127) / 128);
   } else {
-    const int64_t row_wgs = mpad / (64 * na_of(s.nt)) * s.groups;
+    const int64_t row_wgs = mpad / (64 * na_of(ks, s.nt, mixed)) * s.groups;
     const int64_t want = std::max<int64_t>(1, (2048 + row_wgs - 1) / row_wgs);
     s.cps = std::max<int64_t>(2, (nchunks + want - 1) / want);
   }
@@ -849,10 +861,10 @@ static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_in
   return s;
 }
 
-static size_t part_bytes_max(int64_t npad, int64_t mpad, int ntb, bool row_independent) {
+static size_t part_bytes_max(int64_t npad, int64_t mpad, int ntb, bool row_independent, int ks, bool mixed) {
   size_t best = 0;
   for (int nb = 1; nb <= ntb; ++nb) {
-    const SplitChoice s = choose_split(npad, mpad, nb, row_independent);
+    const SplitChoice s = choose_split(npad, mpad, nb, row_independent, ks, mixed);
     best = std::max(best, (size_t)s.nsplit * s.tpad * mpad * sizeof(double));
   }
   return best;
@@ -876,7 +888,7 @@ size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, i
   b += align256((size_t)mpad * 4);                 // nrm_a
   b += align256((size_t)bpad * 8);                 // nrm64
   b += align256((size_t)npad * ntb * 64 + 64);     // vf
-  b += align256(part_bytes_max(npad, mpad, ntb0, !square));  // partials
+  b += align256(part_bytes_max(npad, mpad, ntb0, !square, ks, precision == GP_PREC_BF16X3));  // partials
   return b;
 }
 
@@ -937,7 +949,7 @@ size_t kmm_query_bytes(int precision, int d, int64_t n, int64_t m, int tmax) {
   const int64_t mpad = round_up(m, 256);
   const int ntb = (tmax + 15) / 16;
   return align256((size_t)mpad * ks * 64) + align256((size_t)mpad * 4) + align256((size_t)mpad * 8) +
-         align256(part_bytes_max(npad, mpad, ntb, true));
+         align256(part_bytes_max(npad, mpad, ntb, true, ks, precision == GP_PREC_BF16X3));
 }
 
 bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, int64_t m, int tmax, void* model,
@@ -1300,7 +1312,7 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
                          hipStream_t st, const double* col0) {
   if (t < 1 || t > p.tmax || !p.vf || !V) return hipErrorInvalidValue;
   const int ntb = (t + 15) / 16;
-  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
+  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent, p.ks, p.precision == GP_PREC_BF16X3);
   const int ntb_alloc = sc.groups * sc.nt;  // vf holds whole launch groups (zero padded)
   const int thr = 256;
   if (p.precision == GP_PREC_BF16X3) {
@@ -1382,7 +1394,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   if (!p.xr || !p.xc || !p.nrm_b || !p.nrm_a || !p.vf || !p.part || !out) return hipErrorInvalidValue;
   const bool mixed = p.precision == GP_PREC_BF16X3;
   const int ntb = (t + 15) / 16;
-  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent);
+  const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent, p.ks, p.precision == GP_PREC_BF16X3);
   if (row_independent && mixed && !p.square && ntb <= 4 * kWideNB && p.ks <= 7)
     return kmm_sweep_wide(p, t, sc, Vdiag, ldv, out, ldo, st);
   SweepArgs a;
@@ -1398,7 +1410,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   a.ntb = sc.groups * sc.nt;
   a.tpad = sc.tpad;
   a.square = p.square ? 1 : 0;
-  const int na = na_of(sc.nt);
+  const int na = na_of(p.ks, sc.nt, mixed);
   dim3 grid((unsigned)(p.mpad / (64 * na)), (unsigned)sc.nsplit, (unsigned)sc.groups);
   SweepTiming::Rec rec{};
   bool timed = false;
