@@ -851,7 +851,7 @@ static SplitChoice choose_split(int64_t npad, int64_t mpad, int ntb, bool row_in
   const int64_t nchunks = npad / 32;
   if (row_independent) {
     // depends on n only: each output row sees the same chunk boundaries whatever m is
-    s.cps = std::max<int64_t>(8, (nchunks + 127) / 128);
+    s.cps = std::max<int64_t>(8, (nchunks + 255) / 256);
   } else {
     const int64_t row_wgs = mpad / (64 * na_of(ks, s.nt, mixed)) * s.groups;
     const int64_t want = std::max<int64_t>(1, (2048 + row_wgs - 1) / row_wgs);
