@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
 // loaded during chunk c.  FP32 windows of kFlush chunks are added into the
 // split's FP64 partials (this workgroup owns those slots) in the same order
 // as the sweep above, so each output row's sums depend on n only, not on the
-// batch.  Workgroups are numbered so that the row groups of one split run
+// batch; a split of one window stores it as FP32, which is exact and halves
+// the partials' traffic.  Workgroups are numbered so that the row groups of one split run
 // back to back on one XCD and share the chunk data in its L2.
 constexpr int kWideNB = 5;  // column blocks per wave: 4 waves x 5 x 16 = 320 >= 1 + 256 columns
 
@@ -436,9 +437,10 @@ struct WideArgs {
   const void* xr;  // b stream (training points)
   const void* xc;  // query-row fragments
   const void* vf;  // V fragments, vstride 16-column blocks per chunk
-  double* part;    // [split][tpad][mpad]
+  double* part;    // [split][tpad][mpad], FP64, or FP32 when f32part
   int64_t mpad, nchunks, cps, nsplit;
   int ntb, vstride, tpad, rgroups;
+  int f32part;  // cps <= kFlush: each split is one FP32 window, stored exactly as FP32
 };
 
 template <int KS, int KIND>
@@ -507,7 +509,12 @@ __global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
 #pragma unroll
     for (int jb = 0; jb < kWideNB; ++jb) {
       const int cb = wave + 4 * jb;
-      if (cb < a.ntb) {
+      if (cb < a.ntb && a.f32part) {
+        const int64_t col = (int64_t)cb * 16 + (lane & 15);
+        float* dst = (float*)a.part + (split * a.tpad + col) * a.mpad + row0;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) *(f32x4*)(dst + 16 * rb) = acc[rb][jb];
+      } else if (cb < a.ntb) {
         const int64_t col = (int64_t)cb * 16 + (lane & 15);
         double* dst = a.part + (split * a.tpad + col) * a.mpad + row0;
         double old[4][4];
@@ -724,8 +731,9 @@ __global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsp
 // The split sum of the wide sweep: a workgroup takes one column and 64 rows,
 // wave k adds the splits k, k + 4, ... in split order, and the four sums are
 // then added in wave order, so the order depends on n alone.
-__global__ __launch_bounds__(256) void wide_epilogue_kernel(const double* __restrict__ part, int64_t nsplit,
-                                                            int tpad, int64_t mpad, int64_t m, double sf,
+template <typename T>
+__global__ __launch_bounds__(256) void wide_epilogue_kernel(const T* __restrict__ part, int64_t nsplit, int tpad,
+                                                            int64_t mpad, int64_t m, double sf,
                                                             double* __restrict__ out, int64_t ldo) {
   __shared__ double red[4][64];
   const int r = threadIdx.x & 63;
@@ -734,8 +742,18 @@ __global__ __launch_bounds__(256) void wide_epilogue_kernel(const double* __rest
   const int64_t c = blockIdx.y;
   double s = 0.0;
   if (q < m) {
-#pragma unroll 4
-    for (int64_t sp = k; sp < nsplit; sp += 4) s += part[(sp * tpad + c) * mpad + q];
+    // splits k, k + 4, ... added in that order; eight loads in flight per batch
+    const int64_t step = 4 * (int64_t)tpad * mpad;
+    const T* src = part + ((int64_t)k * tpad + c) * mpad + q;
+    int64_t sp = k;
+    for (; sp + 28 < nsplit; sp += 32, src += 8 * step) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = src[j * step];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += (double)v[j];
+    }
+    for (; sp < nsplit; sp += 4, src += step) s += (double)src[0];
   }
   red[k][r] = s;
   __syncthreads();
@@ -1351,6 +1369,7 @@ static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc,
   a.vstride = sc.groups * sc.nt;  // the V fragments hold whole launch groups
   a.tpad = a.ntb * 16;
   a.rgroups = (int)std::max<int64_t>(1, (p.m + 63) / 64);  // live 64-row groups (mpad is a multiple of 256)
+  a.f32part = sc.cps <= kFlush ? 1 : 0;
   const dim3 grid((unsigned)(a.rgroups * ((sc.nsplit + 7) / 8 * 8)));
   SweepTiming::Rec rec{};
   bool timed = false;
@@ -1384,7 +1403,11 @@ static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc,
     timing().recs.push_back(rec);
   }
   const dim3 egrid((unsigned)((p.m + 63) / 64), (unsigned)t);
-  wide_epilogue_kernel<<<egrid, 256, 0, st>>>(p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf, out, ldo);
+  if (a.f32part)
+    wide_epilogue_kernel<float><<<egrid, 256, 0, st>>>((const float*)p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf,
+                                                       out, ldo);
+  else
+    wide_epilogue_kernel<double><<<egrid, 256, 0, st>>>(p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf, out, ldo);
   return hipGetLastError();
 }
 
