@@ -422,20 +422,43 @@ __global__ void argmax_partial_kernel(const double* __restrict__ delta, int64_t 
 }
 
 // Final argmax over block partials; records the pivot of step m or stops.
-__global__ void argmax_final_kernel(const double* __restrict__ pval, const int64_t* __restrict__ pidx,
-                                    int64_t nblk, PivState ps, int m, double stop_below) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (*ps.rank < m) return;  // already stopped
+// Largest value, lowest index on ties: the answer does not depend on the order
+// in which partials are combined, so one block reduces them as a tree.
+__global__ __launch_bounds__(kThreads) void argmax_final_kernel(const double* __restrict__ pval,
+                                                                const int64_t* __restrict__ pidx, int64_t nblk,
+                                                                PivState ps, int m, double stop_below) {
+  __shared__ double sv[kThreads];
+  __shared__ int64_t si[kThreads];
+  if (*ps.rank < m) return;  // already stopped (the same for every thread)
   double bv = -1.0;
   int64_t bi = -1;
-  for (int64_t b = 0; b < nblk; ++b) {
+  for (int64_t b = threadIdx.x; b < nblk; b += kThreads) {
     const double v = pval[b];
     const int64_t i = pidx[b];
-    if (i >= 0 && (v > bv || (v == bv && i < bi))) {
+    if (i >= 0 && (bi < 0 || v > bv || (v == bv && i < bi))) {
       bv = v;
       bi = i;
     }
   }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double ov = sv[threadIdx.x + off];
+      const int64_t oi = si[threadIdx.x + off];
+      const double mv = sv[threadIdx.x];
+      const int64_t mi = si[threadIdx.x];
+      if (oi >= 0 && (mi < 0 || ov > mv || (ov == mv && oi < mi))) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  bv = sv[0];
+  bi = si[0];
   if (!(bv > stop_below) || bi < 0) {
     return;  // rank stays m
   }
@@ -620,7 +643,7 @@ hipError_t pivchol_launch_argmax(const double* delta, int64_t n, double* pval, i
                                  int m, double stop_below, hipStream_t st) {
   const RowSplit rs = row_split(n, kDotBlocks);
   argmax_partial_kernel<<<(unsigned)rs.nblk, kThreads, 0, st>>>(delta, n, rs.rows_per_blk, pval, pidx);
-  argmax_final_kernel<<<1, 64, 0, st>>>(pval, pidx, rs.nblk, ps, m, stop_below);
+  argmax_final_kernel<<<1, kThreads, 0, st>>>(pval, pidx, rs.nblk, ps, m, stop_below);
   return hipGetLastError();
 }
 
