@@ -379,7 +379,12 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
         }
       }
       bf16x8 H, L;
-      split_bf16x8(mv, H, L);
+      // the one-instruction residual is faster with four column blocks per
+      // tile and slower with one (measured on the same tiles)
+      if constexpr (NT >= 4)
+        split_bf16x8_dot2(mv, H, L);
+      else
+        split_bf16x8(mv, H, L);
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
         acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VH[cb], acc[ab][cb], 0, 0, 0);

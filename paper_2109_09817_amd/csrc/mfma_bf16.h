@@ -41,6 +41,33 @@ __device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& 
   }
 }
 
+// The same split with m - hi (exact in FP32) taken in one instruction
+// per value as the BF16 dot product of the packed hi pair with (-1, 0) or
+// (0, -1), added to m (an input below FP32's normal range may come out as m
+// itself; such a kernel value is far below any tolerance).  The (-1, 0) pair
+// is kept in a register: as an immediate the compiler encodes it as the inline
+// constant -1.0, whose bit pattern the hardware reads as (0, -1).
+__device__ __forceinline__ void split_bf16x8_dot2(const f32x8& m, bf16x8& H, bf16x8& L) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  uint32_t neg_lo_bits = 0x0000bf80u;  // bf16 (-1, 0): low half -1, high half 0
+  asm("" : "+v"(neg_lo_bits));        // opaque to constant folding
+  const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, neg_lo_bits);
+  const bf16x2 neg_hi = __builtin_bit_cast(bf16x2, 0xbf800000u);  // bf16 (0, -1): the FP32 pattern of -1.0
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const f32x2 v = {m[2 * p], m[2 * p + 1]};
+    const bf16x2 h = __builtin_convertvector(v, bf16x2);
+    const f32x2 r = {__builtin_amdgcn_fdot2_f32_bf16(h, neg_lo, v[0], false),
+                     __builtin_amdgcn_fdot2_f32_bf16(h, neg_hi, v[1], false)};
+    const bf16x2 l = __builtin_convertvector(r, bf16x2);
+    H[2 * p] = h[0];
+    H[2 * p + 1] = h[1];
+    L[2 * p] = l[0];
+    L[2 * p + 1] = l[1];
+  }
+}
+
 // K position -> point of a 32-point chunk, for an operand built from the two
 // 16x16 distance accumulators of the chunk (lane l holds rows 4(l/16)+i of
 // each): K = 8(l/16) + j takes point vperm(l/16, j).
