@@ -137,10 +137,12 @@ def test_cross_rows_are_independent_of_the_batch():
 @pytest.mark.parametrize("n,d,t,m,kind", [
     (150_000, 48, 257, 150, ok.MATERN52),  # the prediction shape: 1 + 256 columns, 3 row groups (ragged)
     (140_001, 16, 33, 70, ok.RBF),          # 3 column blocks, 2 row groups
+    (300_007, 16, 33, 70, ok.MATERN52),     # 37 chunks per split: two FP32 windows into FP64 partials
 ])
 def test_long_split_cross_product_matches_oracle(n, d, t, m, kind):
-    # Chunk splits longer than one FP32 window (the FP64 partials are added to),
-    # the widest column set, and the batch independence at that size.
+    # Long chunk splits: up to 32 chunks a split is one FP32 window stored as
+    # FP32; beyond n = 262,144 a split spans several windows added into FP64
+    # partials.  Also the widest column set and the batch independence at size.
     X, th, V = _case(n, d, t, True, seed=11, kind=kind)
     Z = synth.query_molecule("c2", m, seed=7)[:, :d]
     got = _run(th, X, V, "bf16x3", Z=Z)
