@@ -434,8 +434,8 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
 // split's FP64 partials (this workgroup owns those slots) in the same order
 // as the sweep above, so each output row's sums depend on n only, not on the
 // batch; a split of one window stores it as FP32, which is exact and halves
-// the partials' traffic.  Workgroups are numbered so that the row groups of one split run
-// back to back on one XCD and share the chunk data in its L2.
+// the partials' traffic.  Workgroups are numbered so that the row groups of
+// one split run back to back on one XCD and share the chunk data in its L2.
 constexpr int kWideNB = 5;  // column blocks per wave: 4 waves x 5 x 16 = 320 >= 1 + 256 columns
 
 struct WideArgs {
