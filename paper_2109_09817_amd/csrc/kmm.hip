@@ -81,35 +81,53 @@ __device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(f
 // Squared norm of each prepared point (FP64).  BF16X3: n = sum(h^2 + 2 h l), so
 // that the MFMA distance equals |dx'|^2 - |dl|^2 (x' = h + l): its error is
 // relative to the true distance.  FP32: n = sum(f^2) with f = fl32(x~).
-__global__ void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad, int d,
-                                 Scale sc, int mixed, double* __restrict__ nrm) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npad) return;
+__global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad,
+                                                        int d, Scale sc, int mixed, double* __restrict__ nrm) {
+  // Each wave owns 64 consecutive points.  Per slice of 16 features the wave
+  // loads the 64 x 16 block of X (each load instruction covers four rows'
+  // 128-byte runs), turns every element into its norm term and parks the terms
+  // in LDS; lane r then adds row r's terms in feature order, the same sequence
+  // of additions as a per-point loop over the features.
+  constexpr int kF = 16;
+  __shared__ double term[4][64][kF + 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  const int fl = lane & 15;
   double s = 0.0;
-  if (p < n) {
-    const double* x = X + p * d;
-    for (int j0 = 0; j0 < d; j0 += 8) {
-      double v[8];  // eight loads in flight (index clamped into the row); the sum keeps its order
+  if (n > 0) {  // the same for the whole block
+    for (int j0 = 0; j0 < d; j0 += kF) {
+      const int f = j0 + fl < d ? j0 + fl : d - 1;
+      const double scale = sc.s[f];
+      double x[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + q < d ? j0 + q : d - 1;
-        v[q] = x[j] * sc.s[j];
+      for (int k = 0; k < 16; ++k) {  // row 4 k + lane / 16 of the wave's 64 (clamped into X)
+        const int64_t pr = r0 + 4 * k + (lane >> 4);
+        x[k] = X[(pr < n ? pr : n - 1) * d + f];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (j0 + q >= d) break;
+      for (int k = 0; k < 16; ++k) {
+        const int i = 4 * k + (lane >> 4);
+        const double v = x[k] * scale;
+        double t;
         if (mixed) {
-          const double h = bf16_round(v[q]);
-          const double l = bf16_round(v[q] - h);
-          s += h * h + 2.0 * h * l;
+          const double h = bf16_round(v);
+          const double l = bf16_round(v - h);
+          t = h * h + 2.0 * h * l;
         } else {
-          const double f = (float)v[q];
-          s += f * f;
+          const double fv = (float)v;
+          t = fv * fv;
         }
+        term[wave][i][fl] = (r0 + i < n && j0 + fl < d) ? t : 0.0;
       }
+      __syncthreads();
+      const int nf = d - j0 < kF ? d - j0 : kF;
+      for (int q = 0; q < nf; ++q) s += term[wave][lane][q];
+      __syncthreads();  // the next slice overwrites the terms
     }
   }
-  nrm[p] = s;
+  const int64_t p = r0 + lane;
+  if (p < npad) nrm[p] = p < n ? s : 0.0;
 }
 
 // BF16X3 point fragments.  K layout of a prepared point (length 32*KS, zero padded):
