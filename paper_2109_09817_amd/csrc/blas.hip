@@ -221,50 +221,76 @@ __global__ void atb_reduce_kernel(const double* __restrict__ partial, int64_t nb
 __global__ void chol_solve_kernel(const double* __restrict__ Lc, int k, double* __restrict__ Y, int s) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= s) return;
+  // The terms of each dot product are subtracted in index order; their loads
+  // are issued eight at a time so that the chain waits once per eight terms.
   // forward: Lc z = y
   for (int j = 0; j < k; ++j) {
     double v = Y[(int64_t)j * s + c];
-    for (int i = 0; i < j; ++i) v -= Lc[(int64_t)i * k + j] * Y[(int64_t)i * s + c];
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {
+      double lv[8], yv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        lv[u] = Lc[(int64_t)(i + u) * k + j];
+        yv[u] = Y[(int64_t)(i + u) * s + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v -= lv[u] * yv[u];
+    }
+    for (; i < j; ++i) v -= Lc[(int64_t)i * k + j] * Y[(int64_t)i * s + c];
     Y[(int64_t)j * s + c] = v / Lc[(int64_t)j * k + j];
   }
   // backward: Lc^T x = z
   for (int j = k - 1; j >= 0; --j) {
     double v = Y[(int64_t)j * s + c];
-    for (int i = j + 1; i < k; ++i) v -= Lc[(int64_t)j * k + i] * Y[(int64_t)i * s + c];
+    int i = j + 1;
+    for (; i + 8 <= k; i += 8) {
+      double lv[8], yv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        lv[u] = Lc[(int64_t)j * k + i + u];
+        yv[u] = Y[(int64_t)(i + u) * s + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v -= lv[u] * yv[u];
+    }
+    for (; i < k; ++i) v -= Lc[(int64_t)j * k + i] * Y[(int64_t)i * s + c];
     Y[(int64_t)j * s + c] = v / Lc[(int64_t)j * k + j];
   }
 }
 
-// Z = inv_noise * (R - L Y) for columns [c0, c0 + sc), Y row-major k x s.
-// One thread per row; Y staged in LDS in chunks of 64 rows of Y.
-__global__ void woodbury_finish_kernel(const double* __restrict__ L, int k, const double* __restrict__ Y, int s,
-                                       int c0, int sc, const double* __restrict__ R, double* __restrict__ Z,
-                                       int64_t n, double inv_noise) {
-  __shared__ double Ys[64 * 64];
+// Z = inv_noise * (R - L Y) for columns [c0, c0 + sc), sc <= SC, Y row-major k x s.
+// One thread per row with SC accumulators; Y staged in LDS in chunks of 64 rows.
+template <int SC>
+__global__ __launch_bounds__(256) void woodbury_finish_kernel(const double* __restrict__ L, int k,
+                                                              const double* __restrict__ Y, int s, int c0, int sc,
+                                                              const double* __restrict__ R, double* __restrict__ Z,
+                                                              int64_t n, double inv_noise) {
+  __shared__ double Ys[64 * SC];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double acc[64];
+  double acc[SC];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) acc[c] = 0.0;
+  for (int c = 0; c < SC; ++c) acc[c] = 0.0;
   for (int j0 = 0; j0 < k; j0 += 64) {
     const int jn = k - j0 < 64 ? k - j0 : 64;
     __syncthreads();
     for (int e = threadIdx.x; e < jn * sc; e += blockDim.x) {
       const int jj = e / sc, c = e - jj * sc;
-      Ys[jj * 64 + c] = Y[(int64_t)(j0 + jj) * s + c0 + c];
+      Ys[jj * SC + c] = Y[(int64_t)(j0 + jj) * s + c0 + c];
     }
     __syncthreads();
     if (i < n) {
       for (int jj = 0; jj < jn; ++jj) {
         const double l = L[(int64_t)(j0 + jj) * n + i];
 #pragma unroll
-        for (int c = 0; c < 64; ++c)
-          if (c < sc) acc[c] += l * Ys[jj * 64 + c];
+        for (int c = 0; c < SC; ++c)
+          if (c < sc) acc[c] += l * Ys[jj * SC + c];
       }
     }
   }
   if (i >= n) return;
 #pragma unroll
-  for (int c = 0; c < 64; ++c)
+  for (int c = 0; c < SC; ++c)
     if (c < sc) {
       const int64_t o = (int64_t)(c0 + c) * n + i;
       Z[o] = inv_noise * (R[o] - acc[c]);
@@ -560,8 +586,13 @@ hipError_t precond_apply(const Precond& pc, const double* R, double* Z, int64_t 
   chol_solve_kernel<<<blocks_for(s, 64), 64, 0, st>>>(pc.Cchol, pc.rank, Y, s);
   for (int c0 = 0; c0 < s; c0 += 64) {
     const int sc = s - c0 < 64 ? s - c0 : 64;
-    woodbury_finish_kernel<<<blocks_for(n), kThreads, 0, st>>>(pc.L, pc.rank, Y, s, c0, sc, R, Z, n,
-                                                               1.0 / pc.noise);
+    const double inv = 1.0 / pc.noise;
+    if (sc <= 16)
+      woodbury_finish_kernel<16><<<blocks_for(n), kThreads, 0, st>>>(pc.L, pc.rank, Y, s, c0, sc, R, Z, n, inv);
+    else if (sc <= 32)
+      woodbury_finish_kernel<32><<<blocks_for(n), kThreads, 0, st>>>(pc.L, pc.rank, Y, s, c0, sc, R, Z, n, inv);
+    else
+      woodbury_finish_kernel<64><<<blocks_for(n), kThreads, 0, st>>>(pc.L, pc.rank, Y, s, c0, sc, R, Z, n, inv);
   }
   return hipGetLastError();
 }
