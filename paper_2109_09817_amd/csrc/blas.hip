@@ -183,12 +183,24 @@ __global__ void __launch_bounds__(256) atb_partial_kernel(const double* __restri
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
   for (int64_t t0 = r0; t0 < r1; t0 += 64) {
-    // stage A[t0..t0+63][p0..p0+63] and B likewise (zero outside)
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e & 63, col = e >> 6;
-      const int64_t row = t0 + r;
-      As[col][r] = (row < r1 && p0 + col < pa) ? A[(int64_t)(p0 + col) * n + row] : 0.0;
-      Bs[col][r] = (row < r1 && q0 + col < qb) ? B[(int64_t)(q0 + col) * n + row] : 0.0;
+    // stage A[t0..t0+63][p0..p0+63] and B likewise (zero outside): this thread
+    // stages row t0 + tid % 64 of columns tid / 64 + 4 u, all 32 loads issued
+    // before the first store (indexes clamped into the matrices)
+    const int r = tid & 63;
+    const int64_t row = t0 + r;
+    const int64_t rowc = row < n ? row : n - 1;
+    double av[16], bv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int col = (tid >> 6) + 4 * u;
+      av[u] = A[(int64_t)(p0 + col < pa ? p0 + col : pa - 1) * n + rowc];
+      bv[u] = B[(int64_t)(q0 + col < qb ? q0 + col : qb - 1) * n + rowc];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int col = (tid >> 6) + 4 * u;
+      As[col][r] = (row < r1 && p0 + col < pa) ? av[u] : 0.0;
+      Bs[col][r] = (row < r1 && q0 + col < qb) ? bv[u] : 0.0;
     }
     __syncthreads();
     for (int r = 0; r < 64; ++r) {
