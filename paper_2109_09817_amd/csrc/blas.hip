@@ -166,20 +166,22 @@ __global__ void mbcg_init_kernel(MbcgState st) {
 // -------------------------------------------------------- tall-skinny products
 
 // partial[blk][p][q] of G = A^T B over this block's rows, A (n x pa), B (n x qb),
-// both column-major with ld n.  grid = (nblk, ceil(pa/64), ceil(qb/64)),
-// 256 threads, 64-row tiles staged in LDS; each thread owns 16 outputs.
+// both column-major with ld n.  grid = (nblk, ceil(pa/64), ceil(qb/(4 MQ))),
+// 256 threads, 64-row tiles staged in LDS; each thread owns MQ outputs
+// (q = q0 + tid / 64 + 4 m, m < MQ), so a narrow B carries no idle columns.
+template <int MQ>
 __global__ void __launch_bounds__(256) atb_partial_kernel(const double* __restrict__ A, int pa,
                                                           const double* __restrict__ B, int qb, int64_t n,
                                                           int64_t rows_per_blk, double* __restrict__ partial) {
   __shared__ double As[64][65];
-  __shared__ double Bs[64][65];
-  const int p0 = blockIdx.y * 64, q0 = blockIdx.z * 64;
+  __shared__ double Bs[4 * MQ][65];
+  const int p0 = blockIdx.y * 64, q0 = blockIdx.z * (4 * MQ);
   const int tid = threadIdx.x;
   const int pl = tid & 63;        // this thread's p (local)
-  const int qg = tid >> 6;        // q = q0 + qg + 4 m, m = 0..15
-  double acc[16];
+  const int qg = tid >> 6;        // q = q0 + qg + 4 m, m = 0..MQ-1
+  double acc[MQ];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+  for (int m = 0; m < MQ; ++m) acc[m] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
   for (int64_t t0 = r0; t0 < r1; t0 += 64) {
@@ -189,30 +191,31 @@ __global__ void __launch_bounds__(256) atb_partial_kernel(const double* __restri
     const int r = tid & 63;
     const int64_t row = t0 + r;
     const int64_t rowc = row < n ? row : n - 1;
-    double av[16], bv[16];
+    double av[16], bv[MQ];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int col = (tid >> 6) + 4 * u;
       av[u] = A[(int64_t)(p0 + col < pa ? p0 + col : pa - 1) * n + rowc];
-      bv[u] = B[(int64_t)(q0 + col < qb ? q0 + col : qb - 1) * n + rowc];
+      if (u < MQ) bv[u] = B[(int64_t)(q0 + col < qb ? q0 + col : qb - 1) * n + rowc];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int col = (tid >> 6) + 4 * u;
       As[col][r] = (row < r1 && p0 + col < pa) ? av[u] : 0.0;
-      Bs[col][r] = (row < r1 && q0 + col < qb) ? bv[u] : 0.0;
+      if (u < MQ) Bs[col][r] = (row < r1 && q0 + col < qb) ? bv[u] : 0.0;
     }
     __syncthreads();
+#pragma unroll 8
     for (int r = 0; r < 64; ++r) {
       const double av = As[pl][r];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) acc[m] += av * Bs[qg + 4 * m][r];
+      for (int m = 0; m < MQ; ++m) acc[m] += av * Bs[qg + 4 * m][r];
     }
     __syncthreads();
   }
   const int64_t base = (int64_t)blockIdx.x * pa * qb;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
+  for (int m = 0; m < MQ; ++m) {
     const int p = p0 + pl, q = q0 + qg + 4 * m;
     if (p < pa && q < qb) partial[base + (int64_t)p * qb + q] = acc[m];
   }
@@ -561,6 +564,19 @@ hipError_t coldot(const double* A, const double* B, int64_t n, int s, double* ou
   return hipGetLastError();
 }
 
+static void launch_atb_partial(const double* A, int pa, const double* B, int qb, int64_t n, const RowSplit& rs,
+                               double* partial, hipStream_t st) {
+  const unsigned gy = (unsigned)((pa + 63) / 64);
+  if (qb <= 4) {
+    atb_partial_kernel<1><<<dim3((unsigned)rs.nblk, gy, 1), 256, 0, st>>>(A, pa, B, qb, n, rs.rows_per_blk, partial);
+  } else if (qb <= 16) {
+    atb_partial_kernel<4><<<dim3((unsigned)rs.nblk, gy, 1), 256, 0, st>>>(A, pa, B, qb, n, rs.rows_per_blk, partial);
+  } else {
+    atb_partial_kernel<16><<<dim3((unsigned)rs.nblk, gy, (unsigned)((qb + 63) / 64)), 256, 0, st>>>(
+        A, pa, B, qb, n, rs.rows_per_blk, partial);
+  }
+}
+
 size_t atb_partial_doubles(int64_t n, int pa, int qb) {
   const RowSplit rs = row_split(n, kAtbBlocks);
   return (size_t)rs.nblk * pa * qb;
@@ -569,8 +585,7 @@ size_t atb_partial_doubles(int64_t n, int pa, int qb) {
 hipError_t atb(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
                hipStream_t st) {
   const RowSplit rs = row_split(n, kAtbBlocks);
-  dim3 grid((unsigned)rs.nblk, (unsigned)((pa + 63) / 64), (unsigned)((qb + 63) / 64));
-  atb_partial_kernel<<<grid, 256, 0, st>>>(A, pa, B, qb, n, rs.rows_per_blk, partial);
+  launch_atb_partial(A, pa, B, qb, n, rs, partial, st);
   const int64_t pq = (int64_t)pa * qb;
   atb_reduce_kernel<<<blocks_for(pq), kThreads, 0, st>>>(partial, rs.nblk, pq, out);
   return hipGetLastError();
@@ -579,8 +594,7 @@ hipError_t atb(const double* A, int pa, const double* B, int qb, int64_t n, doub
 hipError_t atb_n(const double* A, int pa, const double* B, int qb, int64_t n, double* out, double* partial,
                  int64_t nblk, hipStream_t st) {
   const RowSplit rs = row_split(n, nblk);
-  dim3 grid((unsigned)rs.nblk, (unsigned)((pa + 63) / 64), (unsigned)((qb + 63) / 64));
-  atb_partial_kernel<<<grid, 256, 0, st>>>(A, pa, B, qb, n, rs.rows_per_blk, partial);
+  launch_atb_partial(A, pa, B, qb, n, rs, partial, st);
   const int64_t pq = (int64_t)pa * qb;
   atb_reduce_kernel<<<blocks_for(pq), kThreads, 0, st>>>(partial, rs.nblk, pq, out);
   return hipGetLastError();
