@@ -227,7 +227,15 @@ __global__ void atb_reduce_kernel(const double* __restrict__ partial, int64_t nb
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= pq) return;
   double acc = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) acc += partial[b * pq + e];
+  int64_t b = 0;
+  for (; b + 8 <= nblk; b += 8) {  // eight loads in flight, added in block order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[(b + u) * pq + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; b < nblk; ++b) acc += partial[b * pq + e];
   out[e] = acc;
 }
 
