@@ -20,7 +20,8 @@ Gaussian Process"):
 * ``mbcg``     textbook modified batched preconditioned CG with Lanczos
                tridiagonals, stochastic Lanczos quadrature and trace estimates
                (Sec. 3.1-3.2; mBCG of Gardner et al. 2018 as the paper uses it).
-* ``bcg``      block CG with a shared block Krylov space (Sec. 3.1, Eq. 4).
+* ``altbbmm``  block CG with a shared block Krylov space (Sec. 3.1) and the
+               symmetric Nystrom preconditioner of AltBBMM (Sec. 3.2).
 * ``lanczos``  Lanczos variance cache for fast predictive variances.
 * ``gradient`` the bilinear forms sum_c w_c u_c^T (dK_hat/dtheta) w_c.
 

@@ -21,16 +21,19 @@ import numpy as np
 from .kernel import Theta, profile_of_r2, psi_of_r2, sqdist
 
 
-def bilinear_forms(X, th: Theta, U: np.ndarray, V: np.ndarray, w, block: int = 128) -> np.ndarray:
+def bilinear_forms(X, th: Theta, U: np.ndarray, V: np.ndarray, w, block: int = 128, rows=None) -> np.ndarray:
+    """The d + 2 forms; ``rows = (start, stop)`` restricts the outer sum to rows a in that range
+    (the forms over a partition of the rows add up to the whole)."""
     X = np.asarray(X)
     U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     n, d = X.shape
+    r0, r1 = (0, n) if rows is None else (int(rows[0]), int(rows[1]))
     Xs = X / th.ell
     g = np.zeros(d + 2)
-    for s in range(0, n, block):
-        a = slice(s, min(s + block, n))
+    for s in range(r0, r1, block):
+        a = slice(s, min(s + block, r1))
         r2 = sqdist(X[a], X, th.ell)
         C = (U[a] * w) @ V.T  # C_ab = sum_c w_c U_ac V_bc
         K = th.sf * profile_of_r2(r2, th.kind)
@@ -38,7 +41,7 @@ def bilinear_forms(X, th: Theta, U: np.ndarray, V: np.ndarray, w, block: int = 1
         diff = Xs[a][:, None, :] - Xs[None, :, :]
         g[:d] += np.einsum("ab,abj->j", M, diff * diff)
         g[d] += float(np.sum(K * C))
-    g[d + 1] = th.noise * float(np.sum(w * np.sum(U * V, axis=0)))
+    g[d + 1] = th.noise * float(np.sum(w * np.sum(U[r0:r1] * V[r0:r1], axis=0)))
     return g
 
 

@@ -406,7 +406,7 @@ struct GradGeom {
 static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
   GradGeom g{};
   g.mixed = precision == GP_PREC_BF16X3;
-  g.ks = kmm_ksteps(precision, d);
+  g.ks = g.mixed ? tri_ks_of(d) : kmm_ksteps(precision, d);
   g.npad = (n + 31) / 32 * 32;
   g.nchunks = g.npad / 32;
   if (g.mixed) {
@@ -429,11 +429,17 @@ static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
   return g;
 }
 
+// BF16X3 form: its own four-term distance operands for the mpad rows (>= npad):
+// b-side and a-side fragments and the FP64 norm scratch.
+static size_t dist4_bytes(const GradGeom& g) {
+  return 2 * align256((size_t)g.mpad * g.ks * 64) + align256((size_t)g.mpad * 8);
+}
+
 size_t grad_ws_bytes(int precision, int d, int64_t n, int t) {
   const GradGeom g = grad_geom(precision, d, n, t);
   if (g.ks < 0 || g.ksc < 0) return 0;
   const int64_t nparts = g.nparts();
-  size_t b = kmm_plan_bytes(precision, d, n, n, true, 1);
+  size_t b = g.mixed ? dist4_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
   b += align256((size_t)std::max(g.npad, g.mpad) * g.ksc * 64);  // b-side C fragments
   b += align256((size_t)g.mpad * g.ksc * 64);                    // a-side C fragments
   b += align256((size_t)g.npad * g.ncb * 64);                    // form fragments (hi+lo or float4 pairs)
@@ -479,10 +485,12 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
                  hipStream_t st) {
   const int d = kern->d;
   const GradGeom g = grad_geom(precision, d, n, t);
-  const size_t kb = kmm_plan_bytes(precision, d, n, n, true, 1);
+  if (g.ks < 0 || g.ksc < 0) return fail(GP_EINVAL, "gp_kmm_grad: unsupported d=%d or t=%d", d, t);
+  const size_t kb = g.mixed ? dist4_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
   KmmPlan plan;
-  if (g.ks < 0 || g.ksc < 0 || !kmm_plan_init(plan, kern, precision, n, n, true, 1, ws, kb))
+  if (!g.mixed && !kmm_plan_init(plan, kern, precision, n, n, true, 1, ws, kb))
     return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace too small");
+  if (ws_bytes < align256(kb)) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace too small");
   const int64_t nparts = g.nparts();
   const int64_t nred = (nparts + kRedUnits - 1) / kRedUnits;
   Carve cv((char*)ws + align256(kb), ws_bytes - align256(kb));
@@ -509,8 +517,14 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
     colmean_partial_kernel<<<(unsigned)rs.nblk, 128, 0, st>>>(X, n, d, rs.rows_per_blk, rpart);
     colmean_final_kernel<<<1, 128, 0, st>>>(rpart, rs.nblk, d, n, mu);
   }
-  GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
   const unsigned thr = 256;
+  char* x4r = (char*)ws;  // BF16X3 form: [b-side | a-side | norms] at the front of ws
+  char* x4c = x4r + align256((size_t)g.mpad * g.ks * 64);
+  double* x4n = (double*)(x4c + align256((size_t)g.mpad * g.ks * 64));
+  if (g.mixed)
+    GPK_HIP(prep_dist4(kern, X, n, g.mpad, g.ks, x4r, x4c, x4n, st));
+  else
+    GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
   bool ok = false;
   if (g.mixed) {
     units.reserve((size_t)g.nunits);
@@ -528,8 +542,8 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
                                                                                    g.nchunks, (bf16x8*)gv);
     GPK_HIP(hipGetLastError());
     GradTriArgs a;
-    a.xr = (const bf16x8*)plan.xr;
-    a.xc = (const bf16x8*)plan.xc;
+    a.xr = (const bf16x8*)x4r;
+    a.xc = (const bf16x8*)x4c;
     a.cb = (const bf16x8*)wf;
     a.ca = (const bf16x8*)uf;
     a.gv = (const bf16x8*)gv;

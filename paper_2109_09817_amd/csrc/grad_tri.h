@@ -14,7 +14,8 @@
 // blocks, held in registers) against a range of 32-point chunks b at or after the group's own
 // first chunk; pairs with b <= a inside a chunk that straddles a block are
 // masked.  Per (16 rows) x (32 points) tile, on the BF16 matrix cores:
-//   S    = |x~_a - x~_b|^2          (distance, K = 3d + 6 split terms)
+//   S    = |x~_a - x~_b|^2          (distance, K = 4d + 6: the four products
+//                                    hi.hi + hi.lo + lo.hi + lo.lo and split norms)
 //   C^s  = [W_b | U_b] . [w U_a | w W_a]^T   (K = 2t, split three ways)
 //   P    = psi(S) C^s, its row sums, and sum k(S) C^s   (registers, FP32)
 //   Q, T = P . [x~_b | x~_b^2]       (2 ceil(d/16) blocks of 16 columns)
@@ -31,8 +32,8 @@ namespace gpk {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct GradTriArgs {
-  const bf16x8* xr;     // b-stream distance fragments (A operand)
-  const bf16x8* xc;     // a-row distance fragments (B operand)
+  const bf16x8* xr;     // b-stream four-term distance fragments (A operand)
+  const bf16x8* xc;     // a-row four-term distance fragments (B operand)
   const bf16x8* cb;     // b-stream fragments of [W | U]        (A operand, K = 6t: hi | hi | lo)
   const bf16x8* ca;     // a-row fragments of [w U | w W]       (B operand, K = 6t: hi | lo | hi)
   const bf16x8* gv;     // b-stream fragments of [x~ | x~^2]    (B operand of the forms, hi and lo)
@@ -53,12 +54,27 @@ struct GradTriArgs {
 constexpr int kTriWaves = 4;
 constexpr int kTriFlush = 32;  // chunks per FP32 accumulation window
 
-// 16-row blocks per wave: two while they fit in 256 VGPRs without spilling
+// 16-row blocks per wave: two while they fit in 256 registers without spilling
 // (the staged b-side fragments then serve two tiles per LDS read), else one.
-// The bound is fitted to the compiled register counts of the instantiations.
-constexpr int tri_na(int ks, int ksc, int nj) { return 16 * ks + 8 * ksc + 24 * nj <= 176 ? 2 : 1; }
+// The largest C K-step count with two blocks per (KS, NJ) instantiation is read
+// off the compiled register counts.
+constexpr int tri_max_ksc2(int ks, int nj) {
+  return ks <= 4 && nj == 1 ? 12 : (ks <= 5 && nj <= 3 ? 8 : (ks == 7 && nj == 3 ? 4 : (ks == 7 && nj == 4 ? 2 : 0)));
+}
+constexpr int tri_na(int ks, int ksc, int nj) { return ksc <= tri_max_ksc2(ks, nj) ? 2 : 1; }
 // Rows of one row group (a workgroup's register-resident rows).
 constexpr int tri_rows(int ks, int ksc, int nj) { return 16 * kTriWaves * tri_na(ks, ksc, nj); }
+
+// K steps of 32 of the four-term distance operands for d features (K = 4d + 6),
+// rounded up to the instantiated counts; -1 above d = 64.  The zero K padding
+// is exact.
+inline int tri_ks_of(int d) {
+  const int need = (4 * d + 6 + 31) / 32;
+  static const int kAvail[] = {2, 4, 5, 7, 9};
+  for (int k : kAvail)
+    if (k >= need) return k;
+  return -1;
+}
 
 // Launch one instantiation; false if (ks, nj, ksc) has none.
 bool launch_grad_tri_matern(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st);

@@ -126,26 +126,33 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
     if (more) fetch(ch + 1, cur ^ 1);
     const int64_t b0 = ch * 32;
     if (b0 + 31 > ablk0 * 16) {  // the first block's tile holds some pair b > a
-      bf16x8 B0[KS], B1[KS];  // distance fragments, shared by the NA blocks
+      bool live[NA];
+      f32x4 s0[NA], s1[NA];
+#pragma unroll
+      for (int ab = 0; ab < NA; ++ab) {
+        live[ab] = b0 + 31 > (ablk0 + ab) * 16;
+        s0[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+        s1[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      // distance tiles of the NA blocks, one staged K step at a time (each LDS
+      // read feeds NA MFMAs; only two b-side fragments are live at once)
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        B0[ks] = stage[cur][ks * 64 + lane];
-        B1[ks] = stage[cur][(KS + ks) * 64 + lane];
+        const bf16x8 b0f = stage[cur][ks * 64 + lane];
+        const bf16x8 b1f = stage[cur][(KS + ks) * 64 + lane];
+#pragma unroll
+        for (int ab = 0; ab < NA; ++ab) {
+          if (!live[ab]) continue;
+          s0[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0f, A[ab][ks], s0[ab], 0, 0, 0);
+          s1[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1f, A[ab][ks], s1[ab], 0, 0, 0);
+        }
       }
       bf16x8 H[NA], L[NA];
-      bool live[NA];
 #pragma unroll
       for (int ab = 0; ab < NA; ++ab) {
         const int64_t ar = (ablk0 + ab) * 16;
-        live[ab] = b0 + 31 > ar;
         if (!live[ab]) continue;
-        f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
         f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
-          s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
-        }
 #pragma unroll
         for (int q = 0; q < KSC; ++q) {  // C fragments re-read per block (register budget)
           q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[ab][q], q0, 0, 0, 0);
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
         f32x8 pv;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const float S = __builtin_fabsf(k < 4 ? s0[k] : s1[k - 4]);
+          const float S = __builtin_fabsf(k < 4 ? s0[ab][k] : s1[ab][k - 4]);
           const float cs = k < 4 ? q0[k] : q1[k - 4];
           float m, psi;
           if constexpr (KIND == GP_MATERN52) {
@@ -244,16 +251,19 @@ static bool tri_ksc(int ksc, unsigned units, const GradTriArgs& a, hipStream_t s
   }
 }
 
-// (KS, NJ) pairs that occur for d <= 64: KS = 2 (d <= 19), 4 (d <= 40), 5 (d <= 51), 7 (d <= 64).
+// (KS, NJ) pairs for d <= 64 with the four-term distance (see tri_ks_of):
+//   d <= 14: (2, 1)   d <= 16: (4, 1)   d <= 30: (4, 2)   d <= 32: (5, 2)
+//   d <= 38: (5, 3)   d <= 48: (7, 3)   d <= 54: (7, 4)   d <= 64: (9, 4)
 template <int KIND>
 static bool tri_dispatch(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st) {
   if (ks == 2 && nj == 1) return tri_ksc<2, 1, KIND>(ksc, units, a, st);
-  if (ks == 2 && nj == 2) return tri_ksc<2, 2, KIND>(ksc, units, a, st);
+  if (ks == 4 && nj == 1) return tri_ksc<4, 1, KIND>(ksc, units, a, st);
   if (ks == 4 && nj == 2) return tri_ksc<4, 2, KIND>(ksc, units, a, st);
-  if (ks == 4 && nj == 3) return tri_ksc<4, 3, KIND>(ksc, units, a, st);
+  if (ks == 5 && nj == 2) return tri_ksc<5, 2, KIND>(ksc, units, a, st);
   if (ks == 5 && nj == 3) return tri_ksc<5, 3, KIND>(ksc, units, a, st);
-  if (ks == 5 && nj == 4) return tri_ksc<5, 4, KIND>(ksc, units, a, st);
+  if (ks == 7 && nj == 3) return tri_ksc<7, 3, KIND>(ksc, units, a, st);
   if (ks == 7 && nj == 4) return tri_ksc<7, 4, KIND>(ksc, units, a, st);
+  if (ks == 9 && nj == 4) return tri_ksc<9, 4, KIND>(ksc, units, a, st);
   return false;
 }
 

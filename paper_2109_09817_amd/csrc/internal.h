@@ -77,6 +77,13 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
 // diagonal term of the square product, ignored for cross products).
 hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
                      hipStream_t st, bool row_independent);
+// Four-term BF16 distance operands (|x'_a - x'_b|^2 with x' = h + l, see
+// prep_frag_bf16x4_kernel): K steps of 32 for d features, and the b-side (xr)
+// and a-side (xc) fragments of rows_pad points (a multiple of 64; points >= n
+// are zero), with nrm64 (rows_pad doubles) as scratch for the squared norms.
+int dist4_ksteps(int d);
+hipError_t prep_dist4(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
+                      void* xc, double* nrm64, hipStream_t st);
 // Bytes of the V fragments for t columns.
 size_t kmm_vfrag_bytes(int64_t n, int t);
 // A cross-product plan split in two: the training-side operands (b stream and V

@@ -78,9 +78,11 @@ __device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(f
 
 // ---------------------------------------------------------------- preparation
 
-// Squared norm of each prepared point (FP64).  BF16X3: n = sum(h^2 + 2 h l), so
-// that the MFMA distance equals |dx'|^2 - |dl|^2 (x' = h + l): its error is
-// relative to the true distance.  FP32: n = sum(f^2) with f = fl32(x~).
+// Squared norm of each prepared point (FP64).  mode 1 (three-term BF16 split):
+// n = sum(h^2 + 2 h l), so that the MFMA distance equals |dx'|^2 - |dl|^2
+// (x' = h + l): its error is relative to the true distance.  mode 2 (four-term
+// split, which also carries l.l): n = sum((h + l)^2), so that the MFMA distance
+// is |dx'|^2 itself.  mode 0 (FP32): n = sum(f^2) with f = fl32(x~).
 __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad,
                                                         int d, Scale sc, int mixed, double* __restrict__ nrm) {
   // Each wave owns 64 consecutive points.  Per slice of 16 features the wave
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict
         if (mixed) {
           const double h = bf16_round(v);
           const double l = bf16_round(v - h);
-          t = h * h + 2.0 * h * l;
+          t = mixed == 2 ? (h + l) * (h + l) : h * h + 2.0 * h * l;
         } else {
           const double fv = (float)v;
           t = fv * fv;
@@ -171,6 +173,63 @@ __global__ void prep_frag_bf16x3_kernel(const double* __restrict__ X, const doub
         cv = 1.f;
       } else if (k < 3 * d + 6) {
         const int q = k - 3 * d - 3;
+        rv = 1.f;
+        cv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
+      }
+    }
+    r[j] = (__bf16)rv;
+    c[j] = (__bf16)cv;
+  }
+  if (xr) xr[idx] = r;
+  if (xc) xc[idx] = c;
+}
+
+// Four-term BF16 point fragments (the distances of the hyperparameter-form
+// sweep).  K layout of a prepared point (length 32*KS, zero padded):
+//   row side (b):    [-2h.., -2h.., -2l.., -2l.., nhi, nmid, nlo, 1, 1, 1, 0..]
+//   column side (a): [  h..,   l..,   h..,   l.., 1, 1, 1, nhi, nmid, nlo, 0..]
+// so that sum_K row*col = n_b + n_a - 2 x'_b.x'_a = |x'_a - x'_b|^2 with
+// x' = h + l and n = |x'|^2 (mode 2 of prep_norm_kernel): the dropped l.l
+// product of the three-term form would bias every distance low by about
+// |l_a|^2 + |l_b|^2, a systematic error of ~2^-18 |x~|^2 that does not average
+// out over pairs.  Fragment (blk, ks, lane) holds K = 32 ks + 8 (lane/16) + j of
+// point 16 blk + lane%16.
+__global__ void prep_frag_bf16x4_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
+                                        int64_t n, int64_t nblk, int d, int KS, Scale sc,
+                                        bf16x8* __restrict__ xr, bf16x8* __restrict__ xc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nblk * KS * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t rest = idx >> 6;
+  const int ks = (int)(rest % KS);
+  const int64_t blk = rest / KS;
+  const int64_t p = blk * 16 + (lane & 15);
+  const int g = lane >> 4;
+  bf16x8 r, c;
+  float nhi = 0.f, nmid = 0.f, nlo = 0.f;
+  if (p < n) {
+    const double nn = nrm[p];
+    nhi = bf16_round(nn);
+    nmid = bf16_round(nn - (double)nhi);
+    nlo = bf16_round(nn - (double)nhi - (double)nmid);
+  }
+  for (int j = 0; j < 8; ++j) {
+    const int k = 32 * ks + 8 * g + j;
+    float rv = 0.f, cv = 0.f;
+    if (p < n) {
+      if (k < 4 * d) {
+        const int seg = k / d, f = k - seg * d;
+        const double v = X[p * d + f] * sc.s[f];
+        const float h = bf16_round(v);
+        const float l = bf16_round(v - (double)h);
+        rv = -2.f * (seg < 2 ? h : l);
+        cv = (seg & 1) ? l : h;
+      } else if (k < 4 * d + 3) {
+        const int q = k - 4 * d;
+        rv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
+        cv = 1.f;
+      } else if (k < 4 * d + 6) {
+        const int q = k - 4 * d - 3;
         rv = 1.f;
         cv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
       }
@@ -1291,6 +1350,21 @@ hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, 
 hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st) {
   if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
   return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
+}
+
+int dist4_ksteps(int d) { return d >= 1 && d <= GP_MAX_D ? (4 * d + 6 + 31) / 32 : -1; }
+
+hipError_t prep_dist4(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
+                      void* xc, double* nrm64, hipStream_t st) {
+  if (!X || !nrm64 || (!xr && !xc) || ks < dist4_ksteps(kern->d) || rows_pad % 64 != 0) return hipErrorInvalidValue;
+  const Scale sc = make_scale(kern);
+  const int thr = 256;
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(X, n, rows_pad, kern->d, sc, 2, nrm64);
+  const int64_t nblk = rows_pad / 16;
+  const int64_t total = nblk * ks * 64;
+  prep_frag_bf16x4_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(X, nrm64, n, nblk, kern->d, ks, sc,
+                                                                              (bf16x8*)xr, (bf16x8*)xc);
+  return hipGetLastError();
 }
 
 size_t kmm_vfrag_bytes(int64_t n, int t) {

@@ -1,0 +1,180 @@
+"""Oracle parity at the configured workloads.
+
+* The gradient workload's N = 4096 subsample (the first 4096 rows of the N = 262,144
+  draw: d = 48, 48 lengthscales + s_f + sigma^2, t = 32 probes, rank 100, tol 1e-6):
+  the BBMM mll and every gradient entry against the oracle's estimate on the same probes
+  and pivots (Eq. 2 and its derivatives as estimated in Sec. 3.2), and KhatV's backward
+  against central differences (h = 1e-4 in log theta) of the same bilinear form
+  evaluated with FP64 products.
+* The N = 65,536 model (FP32 products, tol 1e-3) and the N = 131,072 model of the
+  N = 1,048,576 run (BF16x3 products, tol 1e-6): pivots, log|P|, gamma_0, the first
+  CG coefficients, the solve on sampled rows, the SLQ log-determinant, the mll and the
+  gradient against stored oracle results (tests/golden/config_*.json, written by
+  tests/golden/make_config_goldens.py from the oracle alone).
+"""
+import functools
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.kernel as ok
+import synth
+from _helpers import dev, host
+from oracle.bbmm import mll_and_grad_estimate
+from oracle.gradient import bilinear_forms, mll_gradient_forms
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def s3_grad_err(g, ref):
+    """Per-entry gradient error |g_j - ref_j| / max(|ref_j|, 1e-3 max|ref|), maximised over j."""
+    floor = 1e-3 * np.max(np.abs(ref))
+    return float(np.max(np.abs(g - ref) / np.maximum(np.abs(ref), floor)))
+
+
+def _gk(th):
+    from paper_2109_09817_amd import gp
+    return gp.Kernel(th.ell, th.sf, th.noise, "matern52" if th.kind == ok.MATERN52 else "rbf")
+
+
+@functools.lru_cache(maxsize=1)
+def _subsample():
+    """First 4096 rows (whole molecules but the last) of the N = 262,144 gradient workload."""
+    p = synth.make_problem("c4")
+    n = 4096
+    return np.ascontiguousarray(p.X[:n]), np.ascontiguousarray(p.y[:n]), ok.Theta(p.ell, p.sf, p.noise)
+
+
+@functools.lru_cache(maxsize=1)
+def _subsample_oracle():
+    """The oracle's BBMM estimate on the subsample, with the GPU's pivots (equal pivots are
+    checked by the pivoted-Cholesky tests; near-ties may order them differently)."""
+    from paper_2109_09817_amd import gp
+    X, y, th = _subsample()
+    cfg = synth.CONFIGS["c4"]
+    pc = gp.pivchol(_gk(th), dev(X), cfg.rank)
+    piv = [int(v) for v in pc.pivots[:pc.rank]]
+    return mll_and_grad_estimate(X, y, th, t=cfg.probes, k=cfg.rank, seed=5, max_iter=cfg.max_iter,
+                                 tol=cfg.tol, pivots=piv)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_gradient_subsample_matches_oracle(prec):
+    from paper_2109_09817_amd import gp
+    X, y, th = _subsample()
+    cfg = synth.CONFIGS["c4"]
+    r = gp.mll_and_grad(_gk(th), dev(X), dev(y), probes=cfg.probes, rank=cfg.rank, max_iter=cfg.max_iter,
+                        tol=cfg.tol, seed=5, precision=prec)
+    o = _subsample_oracle()
+    e_mll = abs(r.mll - o["mll"]) / abs(o["mll"])
+    e_ld = abs(r.info["logdet"] - o["logdet"]) / abs(o["logdet"])
+    e_g = s3_grad_err(r.grad, o["grad"])
+    log(f"gradient subsample {prec}: mll {r.mll:.6f} oracle {o['mll']:.6f} rel {e_mll:.2e}; "
+        f"logdet rel {e_ld:.2e}; grad per-entry err {e_g:.2e} (50 entries); iters gpu {r.info['iters']} "
+        f"oracle {o['res']['alpha'].shape[0]}")
+    assert r.status == 0
+    assert r.grad.shape == (th.d + 2,) == (50,)
+    assert e_mll <= 1e-4 and e_ld <= 1e-4
+    assert e_g <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_gradient_subsample_central_differences(prec):
+    """KhatV's backward on the subsample's gradient vectors (G_c = w_c U_c, V_c of the mll
+    gradient) against central differences of f(theta) = sum_c G_c . K_hat(theta) V_c with FP64
+    products, h = 1e-4 in every log-hyperparameter; the differences are themselves checked
+    against the oracle's forms."""
+    import torch
+    from paper_2109_09817_amd import autograd as ag
+    from paper_2109_09817_amd import gp
+    X, y, th = _subsample()
+    o = _subsample_oracle()
+    U, V, w = mll_gradient_forms(o["res"]["U"], o["res"]["Z0"], synth.CONFIGS["c4"].probes)
+    G = U * w
+    Xd, Gd, Vd = dev(X), dev(G.T), dev(V.T)
+    v0 = th.log_vector()
+    h = 1e-4
+
+    def f(v):
+        W = gp.kmm(_gk(ok.Theta.from_log(v)), Xd, Vd, precision="fp64")
+        return float(torch.sum(W * Gd))
+
+    fd = np.zeros(v0.shape[0])
+    for j in range(v0.shape[0]):
+        vp, vm = v0.copy(), v0.copy()
+        vp[j] += h
+        vm[j] -= h
+        fd[j] = (f(vp) - f(vm)) / (2 * h)
+    ref = bilinear_forms(X, th, U, V, w)
+    e_fd = s3_grad_err(fd, ref)
+    lt = torch.tensor(v0, requires_grad=True)
+    (ag.KhatV.apply(lt, Xd, Vd, "matern52", prec) * Gd).sum().backward()
+    e_bw = s3_grad_err(lt.grad.numpy(), fd)
+    log(f"central differences (FP64 products, h = 1e-4) against the oracle's forms: {e_fd:.2e}; "
+        f"KhatV backward ({prec}) against the differences: {e_bw:.2e}")
+    assert e_fd <= 1e-6
+    assert e_bw <= 1e-4
+
+
+# ---------------------------------------------------------------- stored oracle results
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"config_{name}.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("name,prec", [("c2", "fp32"), ("c3d", "bf16x3")])
+def test_config_solver_matches_stored_oracle(name, prec):
+    import torch
+    from paper_2109_09817_amd import gp
+    gd = _golden(name)
+    cfg = synth.CONFIGS[name]
+    p = synth.make_problem(name)
+    th = ok.Theta(p.ell, p.sf, p.noise)
+    assert gd["n"] == p.X.shape[0] and abs(gd["y_sum"] - float(np.sum(p.y))) <= 1e-9 * np.sum(np.abs(p.y))
+    g = _gk(th)
+    Xg = dev(p.X)
+    # a4: the preconditioner
+    pc = gp.pivchol(g, Xg, cfg.rank)
+    piv = [int(v) for v in pc.pivots[:pc.rank]]
+    assert piv == gd["pivots"], "pivot order differs from the oracle's"
+    e_lp = abs(pc.logdet - gd["logdet_p"]) / abs(gd["logdet_p"])
+    # a5 + a3: probes and mBCG
+    B = gp.probe_block(dev(p.y), cfg.probes, gd["seed"], th.noise, pc)
+    res = gp.mbcg(g, Xg, B, max_iter=cfg.max_iter, tol=cfg.tol, pc=pc, precision=prec)
+    torch.cuda.synchronize()
+    g0 = np.asarray(gd["gamma0"])
+    e_g0 = float(np.max(np.abs(res.gamma0 - g0) / g0))
+    al = np.asarray(gd["alpha"])
+    J = al.shape[0]
+    assert res.alpha.shape[0] >= J
+    assert [int(i) for i in res.iters] == gd["iters"]
+    e_al = float(np.max(np.abs(res.alpha[:J] - al) / np.where(al != 0, np.abs(al), 1.0)))
+    rows = np.asarray(gd["rows"])
+    Us = host(res.U)[:, rows]
+    Ug = np.asarray(gd["U_rows"])
+    e_u = float(np.max(np.linalg.norm(Us - Ug, axis=1) / np.linalg.norm(Ug, axis=1)))
+    # a6 + a7: the whole evaluation
+    r = gp.mll_and_grad(g, Xg, dev(p.y), probes=cfg.probes, rank=cfg.rank, max_iter=cfg.max_iter, tol=cfg.tol,
+                        seed=gd["seed"], precision=prec)
+    e_ld = abs(r.info["logdet"] - gd["logdet"]) / abs(gd["logdet"])
+    e_mll = abs(r.mll - gd["mll"]) / abs(gd["mll"])
+    e_g = s3_grad_err(r.grad, np.asarray(gd["grad"]))
+    log(f"{name} ({prec}, n={p.X.shape[0]}): log|P| {e_lp:.2e}, gamma0 {e_g0:.2e}, alpha (J={J}) {e_al:.2e}, "
+        f"solve on {rows.size} rows {e_u:.2e}, logdet {e_ld:.2e}, mll {e_mll:.2e}, grad per-entry {e_g:.2e}; "
+        f"iters {res.alpha.shape[0]}")
+    assert res.status == 0 and r.status == 0
+    assert e_lp <= 1e-10 and e_g0 <= 1e-12
+    assert e_al <= 1e-4 and e_u <= 1e-4
+    assert e_ld <= 1e-4 and e_mll <= 1e-4
+    assert e_g <= 1e-4

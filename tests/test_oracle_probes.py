@@ -1,6 +1,8 @@
-"""Pins of the probe generator: integer arithmetic, sign statistics, covariance by enumeration."""
+"""Pins of the probe generator: the published reference outputs, integer arithmetic, sign statistics,
+covariance by enumeration."""
 import itertools
 import math
+import os
 
 import numpy as np
 
@@ -15,6 +17,20 @@ def _splitmix_int(x: int) -> int:
     z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
     z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
     return z ^ (z >> 31)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "splitmix64_reference.txt")
+
+
+def test_splitmix64_matches_published_reference_outputs():
+    # The reference generator's k-th output from seed s is one oracle step applied to the state
+    # s + (k - 1) * 0x9E3779B97F4A7C15 (the step adds the increment once more before mixing).
+    rows = [line.split() for line in open(GOLDEN) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 10
+    for seed, k, hexval in rows:
+        state = (int(seed) + (int(k) - 1) * 0x9E3779B97F4A7C15) & MASK
+        got = int(probes.splitmix64(np.array([state], dtype=np.uint64))[0])
+        assert got == int(hexval, 16), (seed, k)
 
 
 def test_vectorised_uint64_matches_big_integer_arithmetic():
