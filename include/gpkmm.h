@@ -154,6 +154,27 @@ int gp_kmm(const gp_kernel* kern, int32_t precision,
            void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * gp_kmm_noalloc - gp_kmm for callers that cannot allocate device memory at
+ * call time (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same product, arguments and results as gp_kmm, with
+ * its scratch in a fixed array of GP_KMM_NOALLOC_MAX_BYTES that the library
+ * holds on every device it is loaded on until the process ends, instead of a
+ * caller workspace.  The call itself allocates nothing.  Returns GP_EWORKSPACE
+ * (before any GPU work) when the product needs more scratch than that, i.e.
+ * gp_workspace_bytes(GP_OP_KMM, ...) > GP_KMM_NOALLOC_MAX_BYTES (every square
+ * product with n <= 5,500, d <= 48 and t <= 16 fits, in either matrix-core
+ * precision; larger ones may, depending on how the sweep splits).  All calls on one device share
+ * that device's array: calls that overlap in time on one device (different host
+ * threads, or streams not ordered with each other) race.  Asynchronous on
+ * stream; the device is the stream's (the current device for NULL).
+ */
+#define GP_KMM_NOALLOC_MAX_BYTES (64ull << 20)
+int gp_kmm_noalloc(const gp_kernel* kern, int32_t precision,
+                   const double* X, int64_t n, const double* Z, int64_t m,
+                   const double* V, int64_t ldv, int32_t t,
+                   double* out, int64_t ldo, void* stream);
+
+/*
  * gp_kmm_grad - derivative bilinear forms for the gradient of Eq. 2:
  *   grad[j] = sum_c colw[c] * U_c^T (dK_hat / dlog theta_j) W_c
  * with dK_ab/dlog l_j = psi(r_ab) ((x_aj - x_bj)/l_j)^2, dK_hat/dlog s_f = K

@@ -21,6 +21,7 @@ GP_PREC_FP32 = 0
 GP_PREC_BF16X3 = 1
 GP_PREC_FP64 = 2
 GP_MAX_D = 128
+GP_KMM_NOALLOC_MAX_BYTES = 64 << 20
 
 GP_OP_KMM = 1
 GP_OP_KMM_GRAD = 2
@@ -70,6 +71,7 @@ _SZ = C.c_size_t
 
 PROTOTYPES = {
     "gp_kmm": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _I64, _P, _I64, _I32, _P, _I64, _P, _SZ, _P]),
+    "gp_kmm_noalloc": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),
     "gp_kmm_grad": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _I64, _P, _I64, _I32,
                               C.POINTER(_D), C.POINTER(_D), _P, _SZ, _P]),
     "gp_pivchol_precond": (C.c_int, [C.POINTER(GpKernel), _P, _I64, _I32, _P, _P, C.POINTER(C.c_int64),

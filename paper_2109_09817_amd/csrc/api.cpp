@@ -66,9 +66,10 @@ extern "C" const char* gp_last_error(void) { return last_error().c_str(); }
 
 extern "C" const char* gp_version(void) { return "gpkmm 0.1 (gfx950)"; }
 
-extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z,
-                      int64_t m, const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws,
-                      size_t ws_bytes, void* stream) {
+namespace gpk {
+
+int kmm_checked(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z, int64_t m,
+                const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, size_t* need) {
   GPK_TRY(check_kernel(kern));
   GPK_TRY(check_product_precision(precision));
   if (!X) return fail(GP_EINVAL, "gp_kmm: X is NULL");
@@ -80,16 +81,32 @@ extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X,
   const int64_t rows = Z ? m : n;
   if (ldo < rows) return fail(GP_EINVAL, "gp_kmm: ldo=%lld < %lld output rows", (long long)ldo, (long long)rows);
   if ((const void*)out == (const void*)V) return fail(GP_EINVAL, "gp_kmm: out must not alias V");
+  *need = kmm_plan_bytes(precision, kern->d, n, rows, Z == nullptr, t);
+  return GP_OK;
+}
+
+int kmm_run(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z, int64_t m,
+            const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws, size_t ws_bytes,
+            hipStream_t st, bool no_timing) {
   const bool square = Z == nullptr;
-  const size_t need = kmm_plan_bytes(precision, kern->d, n, rows, square, t);
-  GPK_TRY(check_ws(ws, ws_bytes, need, "gp_kmm"));
   KmmPlan p;
-  if (!kmm_plan_init(p, kern, precision, n, rows, square, t, ws, ws_bytes))
+  if (!kmm_plan_init(p, kern, precision, n, square ? n : m, square, t, ws, ws_bytes))
     return fail(GP_EWORKSPACE, "gp_kmm: workspace layout failed");
-  hipStream_t st = (hipStream_t)stream;
+  p.no_timing = no_timing;
   GPK_HIP(kmm_prepare(p, kern, X, Z, st));
   GPK_HIP(kmm_apply(p, V, ldv, t, out, ldo, st, /*row_independent=*/!square));
   return GP_OK;
+}
+
+}  // namespace gpk
+
+extern "C" int gp_kmm(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z,
+                      int64_t m, const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws,
+                      size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  GPK_TRY(kmm_checked(kern, precision, X, n, Z, m, V, ldv, t, out, ldo, &need));
+  GPK_TRY(check_ws(ws, ws_bytes, need, "gp_kmm"));
+  return kmm_run(kern, precision, X, n, Z, m, V, ldv, t, out, ldo, ws, ws_bytes, (hipStream_t)stream, false);
 }
 
 extern "C" int gp_profile_enable(int32_t on) {

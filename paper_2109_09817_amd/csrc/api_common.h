@@ -37,6 +37,14 @@ int check_ws(const void* ws, size_t have, size_t need, const char* op);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// gp_kmm in two steps: argument checks (need receives the workspace bytes), then the
+// product in the given workspace (no_timing: never record profiling events).
+int kmm_checked(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z, int64_t m,
+                const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, size_t* need);
+int kmm_run(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* Z, int64_t m,
+            const double* V, int64_t ldv, int32_t t, double* out, int64_t ldo, void* ws, size_t ws_bytes,
+            hipStream_t st, bool no_timing);
+
 // Bump allocator over the caller's workspace.
 struct Carve {
   char* p;

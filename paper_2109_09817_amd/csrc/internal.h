@@ -39,6 +39,7 @@ struct KmmPlan {
   int tmax = 0;                 // columns the plan was sized for
   int ntb = 0;                  // 16-column blocks for tmax
   double sf = 1.0, noise = 0.0;
+  bool no_timing = false;       // never record profiling events (the allocation-free entry point)
   // workspace carve-out
   void* xr = nullptr;
   void* xc = nullptr;

@@ -1472,7 +1472,7 @@ static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc,
   bool timed = false;
   {
     std::lock_guard<std::mutex> g(timing().mu);
-    timed = timing().on;
+    timed = timing().on && !p.no_timing;
   }
   if (timed) {
     hipError_t e = hipEventCreate(&rec.a);
@@ -1536,7 +1536,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   bool timed = false;
   {
     std::lock_guard<std::mutex> g(timing().mu);
-    timed = timing().on;
+    timed = timing().on && !p.no_timing;
   }
   if (timed) {
     hipError_t e = hipEventCreate(&rec.a);

@@ -91,6 +91,26 @@ def kmm(kern: Kernel, X: torch.Tensor, V: torch.Tensor, Z: Optional[torch.Tensor
     return out
 
 
+def kmm_noalloc(kern: Kernel, X: torch.Tensor, V: torch.Tensor, out: torch.Tensor, Z: Optional[torch.Tensor] = None,
+                precision="bf16x3") -> torch.Tensor:
+    """gp_kmm_noalloc: K_hat V or K(Z, X) V into the caller's ``out`` (t, rows), with the library's
+    fixed device scratch instead of a workspace (no allocation in the call)."""
+    lib = _lib.load()
+    n, d = X.shape
+    _need(X, "X", (n, kern.d))
+    t = V.shape[0]
+    _need(V, "V", (t, n))
+    rows = n if Z is None else Z.shape[0]
+    if Z is not None:
+        _need(Z, "Z", (rows, kern.d))
+    _need(out, "out", (t, rows))
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_kmm_noalloc(C.byref(ks), _prec(precision), X.data_ptr(), n, _ptr(Z),
+                                  rows if Z is not None else 0, V.data_ptr(), n, t, out.data_ptr(), rows,
+                                  _stream(X.device)))
+    return out
+
+
 def kmm_grad(kern: Kernel, X: torch.Tensor, U: torch.Tensor, W: torch.Tensor, colw, precision="fp32") -> np.ndarray:
     """sum_c colw[c] U_c^T (dK_hat/dlog theta) W_c for theta = (l_1..l_d, s_f, sigma^2); U, W (t, n)."""
     lib = _lib.load()

@@ -87,6 +87,24 @@ def test_kmm_rejects_bad_shapes_and_workspace(lib):
     assert b"workspace" in lib.gp_last_error()
 
 
+def test_kmm_noalloc_rejects_on_the_host(lib):
+    """gp_kmm_noalloc checks its arguments as gp_kmm does and refuses products whose scratch exceeds
+    the library's fixed array, both before any GPU work."""
+    from paper_2109_09817_amd import _lib
+    k, keep = _kernel(d=48)
+    fake = 4096  # never dereferenced: validation fails first
+    n = 40000
+    assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, n, 0, 48, 16, 0, 1) > _lib.GP_KMM_NOALLOC_MAX_BYTES
+    assert lib.gp_kmm_noalloc(C.byref(k), 1, fake, n, None, 0, fake, n, 16, fake * 2, n, None) == _lib.GP_EWORKSPACE
+    assert b"scratch" in lib.gp_last_error()
+    assert lib.gp_kmm_noalloc(C.byref(k), 1, None, n, None, 0, fake, n, 16, fake * 2, n, None) == _lib.GP_EINVAL
+    assert lib.gp_kmm_noalloc(C.byref(k), 1, fake, n, None, 0, fake, n, 16, fake, n, None) == _lib.GP_EINVAL
+    assert lib.gp_kmm_noalloc(C.byref(k), 9, fake, 10, None, 0, fake, 10, 2, fake * 2, 10, None) == _lib.GP_EINVAL
+    for n_ok in (1, 333, 2048, 5500):
+        assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, n_ok, 0, 48, 16, 0, 1) <= _lib.GP_KMM_NOALLOC_MAX_BYTES
+        assert lib.gp_workspace_bytes(_lib.GP_OP_KMM, n_ok, 0, 48, 16, 0, 0) <= _lib.GP_KMM_NOALLOC_MAX_BYTES
+
+
 def test_workspace_sizes_are_sane(lib):
     from paper_2109_09817_amd import _lib
     small = lib.gp_workspace_bytes(_lib.GP_OP_KMM, 1000, 0, 48, 16, 0, 1)
