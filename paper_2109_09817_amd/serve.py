@@ -146,6 +146,9 @@ class Server:
             fut.set_exception(ValueError("request rows must be finite"))
             return fut
         with self.cv:
+            if self.stop:
+                fut.set_exception(RuntimeError("prediction server is closed"))
+                return fut
             req = Request(Z, fut, self.clock(), self.next_id)
             self.next_id += 1
             self.queue.append(req)
@@ -161,13 +164,19 @@ class Server:
     # -- scheduler
     def _complete(self, slot):
         reqs, offs, m, nbytes = self.inflight.pop(slot)
-        mean, var = self.ex.fetch(slot, m)
+        self.used -= nbytes
+        try:
+            mean, var = self.ex.fetch(slot, m)
+        except Exception as e:  # a batch whose device work failed fails its own requests only
+            for r in reqs:
+                if not r.future.done():
+                    r.future.set_exception(e)
+            return
         now = self.clock()
         for r, o in zip(reqs, offs):
             k = r.rows.shape[0]
             res = Result(mean[o:o + k].copy(), None if var is None else var[o:o + k].copy(), now - r.t_arrival, m)
             r.future.set_result(res)
-        self.used -= nbytes
         self.completed += len(reqs)
 
     def _admit(self, slot) -> bool:
@@ -204,6 +213,20 @@ class Server:
         return True
 
     def _loop(self):
+        try:
+            self._schedule()
+        except BaseException as e:  # the scheduler cannot go on: no client may wait forever
+            with self.cv:
+                self.stop = True
+                pending = [r for reqs, _, _, _ in self.inflight.values() for r in reqs] + list(self.queue)
+                self.inflight.clear()
+                self.queue.clear()
+            for r in pending:
+                if not r.future.done():
+                    r.future.set_exception(RuntimeError(f"prediction server stopped: {e!r}"))
+            raise
+
+    def _schedule(self):
         while True:
             with self.cv:
                 if self.stop and not self.queue and not self.inflight:

@@ -127,6 +127,10 @@ def test_gradient_subsample_central_differences(prec):
 
 # ---------------------------------------------------------------- stored oracle results
 
+# relative error of the products on well-conditioned data (measured by the gp_kmm parity tests)
+EPS_PRODUCT = {"bf16x3": 3e-5, "fp32": 2e-6}
+
+
 def _golden(name):
     path = os.path.join(GOLDEN, f"config_{name}.json")
     with open(path) as fh:
@@ -159,7 +163,16 @@ def test_config_solver_matches_stored_oracle(name, prec):
     J = al.shape[0]
     assert res.alpha.shape[0] >= J
     assert [int(i) for i in res.iters] == gd["iters"]
-    e_al = float(np.max(np.abs(res.alpha[:J] - al) / np.where(al != 0, np.abs(al), 1.0)))
+    # CG coefficients iteration by iteration.  A relative product error eps perturbs the residual
+    # entering iteration j by about eps ||b||, so alpha_j moves by about kappa eps / (||r_j|| / ||b||);
+    # the residual entering iteration j is sqrt(gamma_j / gamma_0) = sqrt(prod_{i<j} beta_i) in the
+    # P^{-1} norm, and kappa ~ 1.1 on these workloads as configured.
+    be = np.asarray(gd["beta"])
+    rin = np.sqrt(np.vstack([np.ones((1, al.shape[1])), np.cumprod(be, axis=0)])[:J])
+    live = al != 0
+    e_j = np.max(np.where(live, np.abs(res.alpha[:J] - al) / np.where(live, np.abs(al), 1.0), 0.0), axis=1)
+    bound_j = 10.0 * 1.1 * EPS_PRODUCT[prec] / np.min(rin, axis=1)
+    e_al = float(np.max(e_j / bound_j))
     rows = np.asarray(gd["rows"])
     Us = host(res.U)[:, rows]
     Ug = np.asarray(gd["U_rows"])
@@ -170,11 +183,12 @@ def test_config_solver_matches_stored_oracle(name, prec):
     e_ld = abs(r.info["logdet"] - gd["logdet"]) / abs(gd["logdet"])
     e_mll = abs(r.mll - gd["mll"]) / abs(gd["mll"])
     e_g = s3_grad_err(r.grad, np.asarray(gd["grad"]))
-    log(f"{name} ({prec}, n={p.X.shape[0]}): log|P| {e_lp:.2e}, gamma0 {e_g0:.2e}, alpha (J={J}) {e_al:.2e}, "
+    log(f"{name} ({prec}, n={p.X.shape[0]}): log|P| {e_lp:.2e}, gamma0 {e_g0:.2e}, alpha (J={J}) per iteration "
+        f"{np.array2string(e_j, precision=2)} against bounds {np.array2string(bound_j, precision=2)}, "
         f"solve on {rows.size} rows {e_u:.2e}, logdet {e_ld:.2e}, mll {e_mll:.2e}, grad per-entry {e_g:.2e}; "
         f"iters {res.alpha.shape[0]}")
     assert res.status == 0 and r.status == 0
     assert e_lp <= 1e-10 and e_g0 <= 1e-12
-    assert e_al <= 1e-4 and e_u <= 1e-4
+    assert e_al <= 1.0 and e_u <= 1e-4
     assert e_ld <= 1e-4 and e_mll <= 1e-4
     assert e_g <= 1e-4

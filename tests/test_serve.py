@@ -94,6 +94,49 @@ def test_bad_requests_fail_alone():
     srv.close()
 
 
+class FailingFetchExecutor(FakeExecutor):
+    """The device work of batches holding the poison value fails when their results are fetched."""
+
+    def fetch(self, slot, m):
+        Z = self.Z[slot]
+        self.done_at[slot] = None
+        if np.any(Z == -7.5):
+            raise RuntimeError("device error surfaced at fetch")
+        return Z.sum(axis=1), (Z * Z).sum(axis=1)
+
+
+def test_failed_fetch_fails_its_batch_and_serving_continues():
+    ex = FailingFetchExecutor(slots=1, latency=0.002)
+    srv = Server(ex, d=2)
+    bad = srv.submit(np.full((3, 2), -7.5))
+    bad.exception(timeout=10)  # resolved, not hanging
+    good = [srv.submit(np.ones((2, 2)) * i) for i in range(20)]
+    res = [f.result(timeout=10) for f in good]
+    srv.close()
+    assert isinstance(bad.exception(), RuntimeError)
+    assert [float(r.mean[0]) for r in res] == [2.0 * i for i in range(20)]
+    assert srv.used == 0
+
+
+class DyingExecutor(FakeExecutor):
+    """ready() raises: the scheduler thread itself cannot continue."""
+
+    def ready(self, slot):
+        raise MemoryError("scheduler-level failure")
+
+
+def test_scheduler_failure_resolves_every_pending_request():
+    ex = DyingExecutor(slots=1, latency=10.0)
+    srv = Server(ex, d=2)
+    futs = [srv.submit(np.ones((1, 2))) for _ in range(5)]
+    for f in futs:
+        assert isinstance(f.exception(timeout=10), RuntimeError)
+    srv.thread.join(timeout=10)
+    assert not srv.thread.is_alive()
+    late = srv.submit(np.ones((1, 2)))
+    assert isinstance(late.exception(timeout=1), RuntimeError)
+
+
 def test_memory_budget_limits_inflight_batches():
     ex = FakeExecutor(slots=4, latency=0.02)
     srv = Server(ex, d=2, hbm_budget=1000 * 64)  # exactly one full batch fits
