@@ -106,7 +106,8 @@ def main():
                     help="profiling mode: a 1 GiB device copy (traffic calibration) then K products "
                          "K_hat V at n = 917,504, t = 16 (BF16x3), and exit")
     ap.add_argument("--profile-grad", type=int, default=0, metavar="K",
-                    help="profiling mode: K gradient sweeps gp_kmm_grad at n = 917,504, t = 16 (BF16x3), and exit")
+                    help="profiling mode: a 1 GiB device copy (traffic calibration) then K gradient sweeps "
+                         "gp_kmm_grad at n = 917,504, t = 16 (BF16x3), and exit")
     ap.add_argument("--fit-c4", type=int, default=0, metavar="K",
                     help="training mode: K Adam steps (lr 0.05 on log theta, start l = 1, s_f = 1, "
                          "sigma^2 = 1e-2) on the n = 262,144, d = 48 model with t = 32 probes, and exit")
@@ -328,6 +329,11 @@ def profile_grad(args, gp, synth, torch, dev, np):
     U = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 4)).to(dev)
     W = torch.from_numpy(synth.random_block(p.X.shape[0], 16, 5)).to(dev)
     w = np.concatenate([[0.5], np.full(15, -0.5 / 15)])
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB: the traffic counters' calibration copy
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
     ms = []
     for _ in range(args.profile_grad):
         torch.cuda.synchronize()
