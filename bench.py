@@ -530,7 +530,79 @@ def altbbmm_leg(gp, synth, torch, dev, np):
         out[label] = rec
         del pc, res, plain, Bd, X
         torch.cuda.empty_cache()
+    out["paper_rank"] = altbbmm_paper_rank(gp, synth, torch, dev, np)
     return out
+
+
+def altbbmm_paper_rank(gp, synth, torch, dev, np, r=10000):
+    """AltBBMM at the paper's preconditioner rank (Sec. 4: r = 10^4, s = 50, tol 1e-6) on the n = 131,072
+    model: the Cholesky-factor Nystrom preconditioner (FP64 matrix-core products, no eigendecomposition)
+    and block preconditioned CG with FP64 products (the paper's precision) and with BF16x3 products; then
+    the ill-conditioned variant of the n = 65,536 layout with FP64 products, against no preconditioner."""
+    p = synth.make_problem("c3d")
+    n = p.X.shape[0]
+    X = torch.from_numpy(p.X).to(dev)
+    k = gp.Kernel(p.ell, p.sf, p.noise)
+    B = np.vstack([p.y[None, :], synth.random_block(n, 49, 11)])
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    M = np.sort(np.random.default_rng(np.random.SeedSequence([p.cfg.seed, 13])).choice(n, r, replace=False))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc = gp.nystrom_chol_precond(k, X, M)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = p.X.shape[1]
+    build_flops = 2.0 * 2 * n * r * r + 1.0 * n * r * r  # two n x r x r products and the Gram's lower tiles
+    rec = {"n": n, "rank": r, "s": 50, "tol": 1e-6, "build_s": t1 - t0,
+           "build_fp64_tflops_nominal": build_flops / (t1 - t0) / 1e12}
+    log(f"altbbmm rank {r}: Cholesky-factor Nystrom build {t1 - t0:.2f} s")
+    for prec in ("fp64", "bf16x3"):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        res = gp.bpcg(k, X, Bd, 200, 1e-6, pc=pc, precision=prec)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        plain = gp.bpcg(k, X, Bd, 200, 1e-6, pc=None, precision=prec)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        KW = gp.kmm(k, X, res.W[:1].contiguous(), precision="fp64")
+        true = float(torch.linalg.norm(KW[0] - Bd[0]) / torch.linalg.norm(Bd[0]))
+        rec[prec] = {"solve_s": tb - ta, "iters": res.iters, "status": res.status,
+                     "relres_max": float(res.relres.max()), "true_relres_y": true,
+                     "unpreconditioned": {"solve_s": tc - tb, "iters": plain.iters, "status": plain.status}}
+        log(f"altbbmm rank {r} {prec}: {res.iters} it in {tb - ta:.2f} s (true residual {true:.1e}); "
+            f"unpreconditioned {plain.iters} it in {tc - tb:.2f} s")
+        del res, plain, KW
+    del pc, Bd, X
+    torch.cuda.empty_cache()
+    # where the preconditioner pays: the ill-conditioned variant (lengthscales x sqrt(2d)) at n = 65,536
+    q = synth.make_problem("c2", cond_variant=True)
+    nq = q.X.shape[0]
+    Xq = torch.from_numpy(q.X).to(dev)
+    kq = gp.Kernel(q.ell, q.sf, q.noise)
+    Bq = torch.from_numpy(np.ascontiguousarray(np.vstack([q.y[None, :], synth.random_block(nq, 49, 11)]))).to(dev)
+    Mq = np.sort(np.random.default_rng(np.random.SeedSequence([q.cfg.seed, 13])).choice(nq, r, replace=False))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcq = gp.nystrom_chol_precond(kq, Xq, Mq)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = gp.bpcg(kq, Xq, Bq, 1000, 1e-6, pc=pcq, precision="fp64")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plain = gp.bpcg(kq, Xq, Bq, 1000, 1e-6, pc=None, precision="fp64")
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    KW = gp.kmm(kq, Xq, res.W[:1].contiguous(), precision="fp64")
+    true = float(torch.linalg.norm(KW[0] - Bq[0]) / torch.linalg.norm(Bq[0]))
+    rec["c2_ill_conditioned_n65536_fp64"] = {
+        "n": nq, "build_s": t1 - t0, "solve_s": t2 - t1, "iters": res.iters, "status": res.status,
+        "true_relres_y": true, "unpreconditioned": {"solve_s": t3 - t2, "iters": plain.iters, "status": plain.status}}
+    log(f"altbbmm rank {r}, ill-conditioned n={nq} fp64: build {t1 - t0:.2f} s, {res.iters} it in {t2 - t1:.2f} s "
+        f"(true residual {true:.1e}); unpreconditioned {plain.iters} it in {t3 - t2:.2f} s")
+    del pcq, res, plain, KW, Xq, Bq
+    torch.cuda.empty_cache()
+    return rec
 
 
 def cpu_baseline_leg(gp, synth, torch, dev, np, q, t_cols):

@@ -77,6 +77,8 @@ extern "C" {
 #define GP_OP_NYSTROM_APPLY 10
 #define GP_OP_BCG 11
 #define GP_OP_EXACT 12
+#define GP_OP_NYSTROM_CHOL 13
+#define GP_OP_BPCG 14
 
 /*
  * ARD stationary kernel with r^2 = sum_j ((x_j - z_j) / l_j)^2 (Sec. 2.2;
@@ -362,6 +364,50 @@ int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
            const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
            double* W, int64_t ldw, int32_t* iters, double* relres,
            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_nystrom_chol_precond - the AltBBMM Nystrom preconditioner (Sec. 3.2) at
+ * large rank (the paper uses r = 10^4, Sec. 4), built from Cholesky factors
+ * alone (no eigendecomposition):
+ *   K_MM + delta I = L_M L_M^T,   delta = 1e-10 r s_f,
+ *   F = K_XM L_M^{-T}  (n x r),   F^T F + sigma^2 I = L_G L_G^T,
+ *   E = F L_G^{-T}     (n x r),
+ * so that P = F F^T + sigma^2 I (the Nystrom approximation over the landmark
+ * rows M, with K_MM's inverse regularised by delta) and
+ *   P^{-1} = sigma^{-2} (I - E E^T),
+ * positive definite for any rounding of the factors (E E^T has eigenvalues
+ * below 1).  landmarks: host, r distinct indices in [0, n).  E: device n x r,
+ * column-major (ld n), FP64, owned by the caller.  Requires sigma^2 > 0 and
+ * 1 <= r <= min(n, 16384).  Errors: GP_EINVAL, GP_ENOTPD (a factorisation met
+ * a non-positive pivot), GP_EWORKSPACE, GP_EHIP.  Synchronous.  The O(n r^2)
+ * steps (F, F^T F, E) are FP64 matrix-core products.
+ * Workspace: gp_workspace_bytes(GP_OP_NYSTROM_CHOL, n, 0, d, 0, r, any precision)
+ * (an n x r FP64 buffer and two r x r ones).
+ */
+int gp_nystrom_chol_precond(const gp_kernel* kern, const double* X, int64_t n,
+                            const int64_t* landmarks, int32_t r, double* E,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gp_bpcg - AltBBMM solve (Sec. 3.1 block CG, Sec. 3.2) with the preconditioner
+ * of gp_nystrom_chol_precond: block preconditioned CG (O'Leary) on
+ * K_hat W = B with P^{-1} = sigma^{-2} (I - E E^T) (r = 0: P = I, E ignored),
+ *   Q = K_hat D;  alpha = (D^T Q)^{-1} (R^T Z);  W += D alpha;  R -= Q alpha;
+ *   Z = P^{-1} R;  beta = (R_old^T Z_old)^{-1} (R^T Z);  D = Z + D beta,
+ * whose iterates are those of block CG on P^{-1/2} K_hat P^{-1/2} (gp_bcg's
+ * system).  Stops when every column's sqrt(r_c^T P^{-1} r_c) / sqrt(b_c^T P^{-1} b_c)
+ * (that system's relative residual) is <= tol; GP_WNOCONV after max_iter.
+ * K_hat products in `precision` (as gp_kmm); everything else FP64.  B: device
+ * n x s (ldb >= n), nonzero columns, s <= 64; W: device n x s (ldw >= n);
+ * iters: host; relres: host, s entries.  The s x s systems are solved by pivoted
+ * LU on the host; GP_ENOTPD on block breakdown.  Synchronises twice per
+ * iteration.  Workspace: gp_workspace_bytes(GP_OP_BPCG, n, 0, d, s, r, precision).
+ */
+int gp_bpcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n,
+            const double* E, int32_t r,
+            const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol,
+            double* W, int64_t ldw, int32_t* iters, double* relres,
+            void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gp_exact_mll_and_grad - the exact GP of the AltBBMM hyperparameter

@@ -1,4 +1,4 @@
-"""Oracle: AltBBMM, block CG with the symmetric Nystrom preconditioner.
+"""Oracle: AltBBMM, block CG with the symmetric Nystrom preconditioner, and block preconditioned CG.
 
 Test infrastructure only.
 
@@ -88,6 +88,57 @@ def block_cg(matmul, B: np.ndarray, tol: float, max_iter: int) -> dict:
         D = Rn + D @ beta
         R, RtR = Rn, RtRn
     return {"X": X, "iters": iters, "relres": relres, "relres_hist": hist, "alphas": alphas, "betas": betas}
+
+
+def nystrom_matrix_jitter(X, th: Theta, landmarks, jitter_rel: float = 1e-10) -> np.ndarray:
+    """Dense P = K_XM (K_MM + delta I)^{-1} K_MX + sigma^2 I with delta = jitter_rel * r * s_f: the
+    Nystrom approximation with the landmark Gram matrix regularised, as the large-rank
+    preconditioner defines it (a shift of K_MM keeps its inverse bounded when landmark rows nearly
+    repeat)."""
+    M = np.asarray(landmarks, dtype=np.int64)
+    KXM = kernel(X, X[M], th)
+    KMM = KXM[M]
+    delta = jitter_rel * M.shape[0] * th.sf
+    Q = KXM @ np.linalg.solve(KMM + delta * np.eye(M.shape[0]), KXM.T)
+    Q = 0.5 * (Q + Q.T)
+    return Q + th.noise * np.eye(X.shape[0])
+
+
+def block_pcg(matmul, B: np.ndarray, precond, tol: float, max_iter: int) -> dict:
+    """Block preconditioned CG (O'Leary) on the SPD operator ``matmul`` with ``precond(R)`` = P^{-1} R,
+    from W = 0, R = B, Z = P^{-1} R, D = Z:
+        Q = A D;  alpha = (D^T Q)^{-1} (R^T Z);  W += D alpha;  R_new = R - Q alpha
+        stop when sqrt(r_c^T P^{-1} r_c) <= tol sqrt(b_c^T P^{-1} b_c) for every column c
+        Z_new = P^{-1} R_new;  beta = (R^T Z)^{-1} (R_new^T Z_new);  D = Z_new + D beta."""
+    B = np.asarray(B, dtype=np.float64)
+    n, s = B.shape
+    W = np.zeros((n, s))
+    R = B.copy()
+    Z = precond(R)
+    D = Z.copy()
+    RtZ = R.T @ Z
+    bnorm = np.sqrt(np.diag(RtZ))
+    alphas, betas, hist = [], [], []
+    relres = np.ones(s)
+    iters = 0
+    for k in range(max_iter):
+        Q = matmul(D)
+        alpha = np.linalg.solve(D.T @ Q, RtZ)
+        W = W + D @ alpha
+        Rn = R - Q @ alpha
+        Zn = precond(Rn)
+        RtZn = Rn.T @ Zn
+        iters = k + 1
+        alphas.append(alpha)
+        relres = np.sqrt(np.maximum(np.diag(RtZn), 0.0)) / bnorm
+        hist.append(relres.copy())
+        if np.all(relres <= tol):
+            break
+        beta = np.linalg.solve(RtZ, RtZn)
+        betas.append(beta)
+        D = Zn + D @ beta
+        R, Z, RtZ = Rn, Zn, RtZn
+    return {"W": W, "iters": iters, "relres": relres, "relres_hist": hist, "alphas": alphas, "betas": betas}
 
 
 def altbbmm_solve(X, th: Theta, B: np.ndarray, landmarks, tol: float, max_iter: int, rcond: float = 0.0) -> dict:

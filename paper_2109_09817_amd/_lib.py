@@ -35,6 +35,8 @@ GP_OP_NYSTROM = 9
 GP_OP_NYSTROM_APPLY = 10
 GP_OP_BCG = 11
 GP_OP_EXACT = 12
+GP_OP_NYSTROM_CHOL = 13
+GP_OP_BPCG = 14
 
 
 class GpKernel(C.Structure):
@@ -96,6 +98,10 @@ PROTOTYPES = {
                                          C.POINTER(C.c_double), _P, _P, _SZ, _P]),
     "gp_bcg": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _P, _I32, _P, _I64, _I32, _I32, _D, _P, _I64,
                          C.POINTER(_I32), C.POINTER(_D), _P, _SZ, _P]),
+    "gp_nystrom_chol_precond": (C.c_int, [C.POINTER(GpKernel), _P, _I64, C.POINTER(C.c_int64), _I32, _P, _P, _SZ,
+                                          _P]),
+    "gp_bpcg": (C.c_int, [C.POINTER(GpKernel), _I32, _P, _I64, _P, _I32, _P, _I64, _I32, _I32, _D, _P, _I64,
+                          C.POINTER(_I32), C.POINTER(_D), _P, _SZ, _P]),
     "gp_workspace_bytes": (C.c_size_t, [_I32, _I64, _I64, _I32, _I32, _I32, _I32]),
     "gp_profile_enable": (C.c_int, [_I32]),
     "gp_profile_read": (C.c_int, [C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), _I32]),

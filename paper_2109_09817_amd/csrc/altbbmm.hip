@@ -160,6 +160,12 @@ static hipError_t tall_product_wide(const double* A, int64_t nrows, int kk, cons
   return hipSuccess;
 }
 
+// out[e] = a in[e] for e < count.
+__global__ void tall_scale_kernel(const double* __restrict__ in, int64_t count, double a, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) out[e] = a * in[e];
+}
+
 // out[e] = g[e / s] in[e] for e < r s (rows of an r x s row-major block).
 __global__ void scale_rows_kernel(const double* __restrict__ in, const double* __restrict__ g, int r, int s,
                                   double* __restrict__ out) {
@@ -441,6 +447,238 @@ int run_bcg(const gp_kernel* kern, int precision, const double* X, int64_t n, co
   return converged ? GP_OK : GP_WNOCONV;
 }
 
+// ---------------------------------------------------------------- large rank: Cholesky factor form
+//
+// At the paper's rank (r = 10^4, Sec. 4) the two r x r eigendecompositions of
+// the spectral form are out of reach on the host.  The same Nystrom
+// approximation is then carried by Cholesky factors only:
+//
+//   K_MM + delta I = L_M L_M^T          (delta = kNysCholJitter r s_f)
+//   F = K_XM L_M^{-T}                   (n x r; F F^T = K_XM (K_MM + delta I)^{-1} K_MX)
+//   F^T F + sigma^2 I = L_G L_G^T
+//   E = F L_G^{-T}                      (n x r)
+//   P = F F^T + sigma^2 I,   P^{-1} = sigma^{-2} (I - E E^T).
+//
+// E E^T = F (F^T F + sigma^2 I)^{-1} F^T has eigenvalues s / (s + sigma^2) < 1
+// (s the eigenvalues of F^T F), so the P^{-1} applied is positive definite
+// however the factors round: the Gram matrix is formed from F itself, never as
+// L_M^{-1} K_MX K_XM L_M^{-T}.  The jitter bounds cond(K_MM + delta I) by
+// about 1 / kNysCholJitter (nearly repeated landmark rows make K_MM singular)
+// and keeps P an under-approximation of K_hat.  The O(n r^2) products (F, the
+// Gram matrix, E) run on the FP64 matrix cores (dense_gemm), the two
+// factorisations and triangular inverses on blocked FP64 tile kernels.
+//
+// The solver with this preconditioner is block preconditioned CG (O'Leary) on
+// K_hat W = B with P^{-1}: its iterates are those of block CG on the
+// symmetrically preconditioned P^{-1/2} K_hat P^{-1/2} (the form of gp_bcg), and
+// its residual norm sqrt(r^T P^{-1} r) is that system's residual norm.
+
+constexpr int kNysCholMaxR = 16384;
+constexpr double kNysCholJitter = 1e-10;
+
+__global__ void add_diag_kernel(double* __restrict__ A, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[i * n + i] += v;
+}
+
+// M[i] = i (the landmark rows gathered into their own matrix)
+__global__ void iota_kernel(int64_t* __restrict__ M, int r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < r) M[i] = i;
+}
+
+__global__ void gather_rows_kernel(const double* __restrict__ X, int d, const int64_t* __restrict__ M, int r,
+                                   double* __restrict__ XM) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * d) return;
+  const int64_t i = e / d, f = e - i * d;
+  XM[e] = X[M[i] * d + f];
+}
+
+size_t nystrom_chol_ws_bytes(int d, int64_t n, int r) {
+  size_t b = 0;
+  b += 2 * align256((size_t)r * 8);                 // landmark indices, iota
+  b += align256((size_t)d * 8);                     // feature scales
+  b += align256((size_t)r * d * 8);                 // landmark rows
+  b += 2 * align256((size_t)r * r * 8);             // K_MM -> L_M -> G -> L_G; L^{-1}
+  b += align256(dense_dinv_doubles(r) * 8);         // diagonal-block inverses
+  b += align256((size_t)n * r * 8);                 // K_XM, later E^T
+  b += align256(sizeof(int) * 2);                   // Cholesky status
+  return b + 4096;
+}
+
+int run_nystrom_chol(const gp_kernel* kern, const double* X, int64_t n, const int64_t* landmarks, int r, double* E,
+                     void* ws, size_t ws_bytes, hipStream_t st) {
+  const int d = kern->d;
+  Carve cv(ws, ws_bytes);
+  int64_t* Mdev = cv.take<int64_t>(r);
+  int64_t* iota = cv.take<int64_t>(r);
+  double* scd = cv.take<double>(d);
+  double* XM = cv.take<double>((size_t)r * d);
+  double* A = cv.take<double>((size_t)r * r);
+  double* Linv = cv.take<double>((size_t)r * r);
+  double* Dinv = cv.take<double>(dense_dinv_doubles(r));
+  double* T = cv.take<double>((size_t)n * r);
+  int* info = cv.take<int>(2);
+  if (!info) return fail(GP_EWORKSPACE, "gp_nystrom_chol_precond: workspace layout failed");
+  std::vector<double> sc(d);
+  for (int f = 0; f < d; ++f) sc[f] = (kern->kind == GP_MATERN52 ? std::sqrt(5.0) : 1.0) / kern->lengthscale[f];
+  const int zero[2] = {0, 0};
+  GPK_HIP(hipMemcpyAsync(Mdev, landmarks, sizeof(int64_t) * r, hipMemcpyHostToDevice, st));
+  GPK_HIP(hipMemcpyAsync(scd, sc.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
+  GPK_HIP(hipMemcpyAsync(info, zero, sizeof(zero), hipMemcpyHostToDevice, st));
+  const unsigned thr = 256;
+  iota_kernel<<<(unsigned)((r + thr - 1) / thr), thr, 0, st>>>(iota, r);
+  gather_rows_kernel<<<(unsigned)(((int64_t)r * d + thr - 1) / thr), thr, 0, st>>>(X, d, Mdev, r, XM);
+  GPK_HIP(hipGetLastError());
+  // K_XM column by column (column j = K(X, x_{M_j})) = K_MX row-major r x n; K_MM likewise from the landmark rows
+  auto kcols = [&](const double* P, int64_t np, const int64_t* idx, double* out) {
+    dim3 grid((unsigned)((np + 255) / 256), (unsigned)((r + kNysTile - 1) / kNysTile));
+    if (kern->kind == GP_MATERN52)
+      kernel_cols_kernel<GP_MATERN52><<<grid, 256, 0, st>>>(P, np, d, scd, idx, r, kern->outputscale, out);
+    else
+      kernel_cols_kernel<GP_RBF><<<grid, 256, 0, st>>>(P, np, d, scd, idx, r, kern->outputscale, out);
+  };
+  kcols(X, n, Mdev, T);
+  kcols(XM, r, iota, A);
+  GPK_HIP(hipGetLastError());
+  // L_M L_M^T = K_MM + delta I (lower triangle), L_M^{-1}
+  add_diag_kernel<<<(unsigned)((r + thr - 1) / thr), thr, 0, st>>>(A, r, kNysCholJitter * r * kern->outputscale);
+  GPK_HIP(hipGetLastError());
+  GPK_HIP(dense_cholesky(A, r, info, Dinv, st));
+  GPK_HIP(dense_lower_inverse(A, Linv, Dinv, r, st));
+  // F^T = L_M^{-1} K_MX (r x n row-major, i.e. F column-major), into E
+  GPK_HIP(dense_gemm(false, false, false, r, n, r, Linv, r, T, n, E, n, st));
+  // G = F^T F + sigma^2 I (lower tiles), L_G, L_G^{-1}
+  GPK_HIP(dense_gemm(false, true, true, r, r, n, E, n, E, n, A, r, st));
+  add_diag_kernel<<<(unsigned)((r + thr - 1) / thr), thr, 0, st>>>(A, r, kern->noise);
+  GPK_HIP(hipGetLastError());
+  GPK_HIP(dense_cholesky(A, r, info + 1, Dinv, st));
+  GPK_HIP(dense_lower_inverse(A, Linv, Dinv, r, st));
+  // E^T = L_G^{-1} F^T (r x n row-major = E column-major)
+  GPK_HIP(dense_gemm(false, false, false, r, n, r, Linv, r, E, n, T, n, st));
+  GPK_HIP(hipMemcpyAsync(E, T, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+  int h_info[2] = {0, 0};
+  GPK_HIP(hipMemcpyAsync(h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, st));
+  GPK_HIP(hipStreamSynchronize(st));
+  if (h_info[0] != 0)
+    return fail(GP_ENOTPD, "gp_nystrom_chol_precond: K_MM + jitter not positive definite (pivot %d)", h_info[0] - 1);
+  if (h_info[1] != 0)
+    return fail(GP_ENOTPD, "gp_nystrom_chol_precond: F^T F + sigma^2 I not positive definite (pivot %d)", h_info[1] - 1);
+  return GP_OK;
+}
+
+// Y = P^{-1} V = sigma^{-2} (V - E (E^T V)) for an n x s block (ld n); Y may alias V.
+static hipError_t nystrom_chol_apply(const double* E, int64_t n, int r, double noise, const double* V, int s,
+                                     double* Y, double* C1, double* C2, double* part, hipStream_t st) {
+  hipError_t e;
+  if ((e = gram(E, r, V, s, n, C1, part, st)) != hipSuccess) return e;
+  const double inv = 1.0 / noise;
+  // C2 = -sigma^{-2} C1
+  tall_scale_kernel<<<(unsigned)(((int64_t)r * s + 255) / 256), 256, 0, st>>>(C1, (int64_t)r * s, -inv, C2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return tall_product(E, n, n, r, C2, s, s, inv, V, n, Y, n, false, st);
+}
+
+size_t bpcg_ws_bytes(int precision, int d, int64_t n, int r, int s) {
+  size_t b = kmm_plan_bytes(precision, d, n, n, true, s);
+  b += 5 * align256((size_t)n * s * 8);                              // U, R, Z, D, Q
+  b += 2 * align256((size_t)std::max(r, 1) * s * 8);                 // E^T V and its scaled copy
+  b += align256(std::max(gram_partial_doubles(n, std::max(r, 1), s), gram_partial_doubles(n, s, s)) * 8);
+  b += 3 * align256((size_t)s * s * 8);                              // Gram out, alpha, beta
+  return b + 4096;
+}
+
+int run_bpcg(const gp_kernel* kern, int precision, const double* X, int64_t n, const double* E, int r,
+             const double* B, int64_t ldb, int s, int max_iter, double tol, double* W, int64_t ldw, int32_t* iters_out,
+             double* relres, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int d = kern->d;
+  const size_t kb = kmm_plan_bytes(precision, d, n, n, true, s);
+  KmmPlan plan;
+  if (!kmm_plan_init(plan, kern, precision, n, n, true, s, ws, kb)) return fail(GP_EWORKSPACE, "gp_bpcg: workspace too small");
+  Carve cv((char*)ws + align256(kb), ws_bytes - align256(kb));
+  const size_t ns = (size_t)n * s;
+  double* U = cv.take<double>(ns);
+  double* R = cv.take<double>(ns);
+  double* Zb = cv.take<double>(ns);
+  double* D = cv.take<double>(ns);
+  double* Q = cv.take<double>(ns);
+  double* C1 = cv.take<double>((size_t)std::max(r, 1) * s);
+  double* C2 = cv.take<double>((size_t)std::max(r, 1) * s);
+  double* part = cv.take<double>(std::max(gram_partial_doubles(n, std::max(r, 1), s), gram_partial_doubles(n, s, s)));
+  double* Gd = cv.take<double>((size_t)s * s);
+  double* Ad = cv.take<double>((size_t)s * s);
+  double* Bd = cv.take<double>((size_t)s * s);
+  if (!Bd) return fail(GP_EWORKSPACE, "gp_bpcg: workspace layout failed");
+  auto precond = [&](const double* in, double* out) -> hipError_t {
+    if (r > 0) return nystrom_chol_apply(E, n, r, kern->noise, in, s, out, C1, C2, part, st);
+    return hipMemcpyAsync(out, in, sizeof(double) * ns, hipMemcpyDeviceToDevice, st);
+  };
+  auto gram_host = [&](const double* A, const double* Bm, std::vector<double>& out) -> hipError_t {
+    hipError_t e = gram(A, s, Bm, s, n, Gd, part, st);
+    if (e != hipSuccess) return e;
+    out.resize((size_t)s * s);
+    e = hipMemcpyAsync(out.data(), Gd, sizeof(double) * s * s, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  };
+  // R = B, Z = P^{-1} R, D = Z, U = 0
+  for (int c = 0; c < s; ++c)
+    GPK_HIP(hipMemcpyAsync(R + (size_t)c * n, B + (size_t)c * ldb, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  GPK_HIP(precond(R, Zb));
+  GPK_HIP(hipMemcpyAsync(D, Zb, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
+  GPK_HIP(launch_fill(U, 0.0, (int64_t)ns, st));
+  GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
+  std::vector<double> RtZ, RtZn, DtQ, alpha, nalpha, beta;
+  GPK_HIP(gram_host(R, Zb, RtZ));
+  std::vector<double> bnorm(s);
+  for (int c = 0; c < s; ++c) {
+    bnorm[c] = std::sqrt(std::max(RtZ[(size_t)c * s + c], 0.0));
+    if (!std::isfinite(bnorm[c])) return fail(GP_ENONFINITE, "gp_bpcg: non-finite right-hand side");
+    if (!(bnorm[c] > 0.0)) return fail(GP_EINVAL, "gp_bpcg: right-hand side column %d is zero", c);
+    relres[c] = 1.0;
+  }
+  int it = 0;
+  bool converged = false;
+  while (it < max_iter) {
+    GPK_HIP(kmm_apply(plan, D, n, s, Q, n, st, false));
+    GPK_HIP(gram_host(D, Q, DtQ));
+    if (!host_lu_solve(DtQ, s, RtZ, alpha))
+      return fail(GP_ENOTPD, "gp_bpcg: D^T K_hat D singular at iteration %d (block breakdown)", it);
+    nalpha = alpha;
+    for (auto& v : nalpha) v = -v;
+    GPK_HIP(hipMemcpyAsync(Ad, alpha.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+    GPK_HIP(hipMemcpyAsync(Bd, nalpha.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+    GPK_HIP(tall_product(D, n, n, s, Ad, s, s, 1.0, U, n, U, n, false, st));   // U += D alpha
+    GPK_HIP(tall_product(Q, n, n, s, Bd, s, s, 1.0, R, n, R, n, false, st));   // R -= Q alpha
+    GPK_HIP(precond(R, Zb));
+    GPK_HIP(gram_host(R, Zb, RtZn));  // also orders the uploads above before alpha is rewritten
+    ++it;
+    bool all = true;
+    for (int c = 0; c < s; ++c) {
+      relres[c] = std::sqrt(std::max(RtZn[(size_t)c * s + c], 0.0)) / bnorm[c];
+      if (!std::isfinite(relres[c])) return fail(GP_ENONFINITE, "gp_bpcg: non-finite residual at iteration %d", it);
+      all = all && relres[c] <= tol;
+    }
+    if (all) {
+      converged = true;
+      break;
+    }
+    if (it == max_iter) break;
+    if (!host_lu_solve(RtZ, s, RtZn, beta))
+      return fail(GP_ENOTPD, "gp_bpcg: R^T P^{-1} R singular at iteration %d (block breakdown)", it);
+    GPK_HIP(hipMemcpyAsync(Bd, beta.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+    GPK_HIP(tall_product(D, n, n, s, Bd, s, s, 1.0, Zb, n, D, n, false, st));   // D = Z + D beta
+    RtZ.swap(RtZn);
+    GPK_HIP(hipStreamSynchronize(st));  // beta's upload completes before the host vector is reused
+  }
+  for (int c = 0; c < s; ++c)
+    GPK_HIP(hipMemcpyAsync(W + (size_t)c * ldw, U + (size_t)c * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  GPK_HIP(hipStreamSynchronize(st));
+  *iters_out = it;
+  return converged ? GP_OK : GP_WNOCONV;
+}
+
 }  // namespace gpk
 
 using namespace gpk;
@@ -500,4 +738,36 @@ extern "C" int gp_bcg(const gp_kernel* kern, int32_t precision, const double* X,
   GPK_TRY(check_ws(ws, ws_bytes, bcg_ws_bytes(precision, kern->d, n, r, s), "gp_bcg"));
   return run_bcg(kern, precision, X, n, Z, g, r, B, ldb, s, max_iter, tol, W, ldw, iters, relres, ws, ws_bytes,
                  (hipStream_t)stream);
+}
+
+extern "C" int gp_nystrom_chol_precond(const gp_kernel* kern, const double* X, int64_t n, const int64_t* landmarks,
+                                       int32_t r, double* E, void* ws, size_t ws_bytes, void* stream) {
+  GPK_TRY(check_kernel(kern));
+  if (!X || !landmarks || !E) return fail(GP_EINVAL, "gp_nystrom_chol_precond: NULL argument");
+  if (n < 1) return fail(GP_EINVAL, "gp_nystrom_chol_precond: n must be >= 1");
+  if (r < 1 || r > kNysCholMaxR || r > n)
+    return fail(GP_EINVAL, "gp_nystrom_chol_precond: r=%d outside [1, min(n, %d)]", r, kNysCholMaxR);
+  if (!(kern->noise > 0.0)) return fail(GP_EINVAL, "gp_nystrom_chol_precond: the noise must be > 0");
+  GPK_TRY(check_landmarks(landmarks, r, n));
+  GPK_TRY(check_ws(ws, ws_bytes, nystrom_chol_ws_bytes(kern->d, n, r), "gp_nystrom_chol_precond"));
+  return run_nystrom_chol(kern, X, n, landmarks, r, E, ws, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int gp_bpcg(const gp_kernel* kern, int32_t precision, const double* X, int64_t n, const double* E,
+                       int32_t r, const double* B, int64_t ldb, int32_t s, int32_t max_iter, double tol, double* W,
+                       int64_t ldw, int32_t* iters, double* relres, void* ws, size_t ws_bytes, void* stream) {
+  GPK_TRY(check_kernel(kern));
+  GPK_TRY(check_product_precision(precision));
+  if (!X || !B || !W || !iters || !relres) return fail(GP_EINVAL, "gp_bpcg: NULL argument");
+  if (n < 1) return fail(GP_EINVAL, "gp_bpcg: n must be >= 1");
+  if (s < 1 || s > kTallMaxS) return fail(GP_EINVAL, "gp_bpcg: s=%d outside [1, %d]", s, kTallMaxS);
+  if (ldb < n || ldw < n) return fail(GP_EINVAL, "gp_bpcg: ldb and ldw must be >= n");
+  if (max_iter < 1) return fail(GP_EINVAL, "gp_bpcg: max_iter must be >= 1");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(GP_EINVAL, "gp_bpcg: tol must be finite and >= 0");
+  if (r < 0 || r > kNysCholMaxR || r > n) return fail(GP_EINVAL, "gp_bpcg: r=%d outside [0, min(n, %d)]", r, kNysCholMaxR);
+  if (r > 0 && !E) return fail(GP_EINVAL, "gp_bpcg: r > 0 needs E");
+  if (r > 0 && !(kern->noise > 0.0)) return fail(GP_EINVAL, "gp_bpcg: the preconditioner needs noise > 0");
+  GPK_TRY(check_ws(ws, ws_bytes, bpcg_ws_bytes(precision, kern->d, n, r, s), "gp_bpcg"));
+  return run_bpcg(kern, precision, X, n, E, r, B, ldb, s, max_iter, tol, W, ldw, iters, relres, ws, ws_bytes,
+                  (hipStream_t)stream);
 }

@@ -339,6 +339,95 @@ static hipError_t tile_update(const double* Pm, int64_t ldp, int64_t pfix, int64
   return hipGetLastError();
 }
 
+// General FP64 product C = A B (m x nn, row-major with ldc) on the matrix
+// cores, 64 x 64 output tiles, k in chunks of 64 staged in LDS as in the tile
+// kernel above:  A(i, k) = TA ? A[k lda + i] : A[i lda + k],
+//                B(k, j) = TB ? B[j ldb + k] : B[k ldb + j].
+// LOWER computes only the tiles with tj <= ti (m = nn).  Rows, columns and k
+// beyond the matrices read as zero; nothing outside C's m x nn block is written.
+template <bool TA, bool TB, bool LOWER>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const double* A, int64_t lda, const double* B, int64_t ldb,
+                                                       double* C, int64_t ldc, int64_t m, int64_t nn, int64_t kk,
+                                                       int nrt, int nct) {
+  __shared__ double As[kEb * kKMajorLd];  // A(r, k) at lds_at<TA>(k, r)
+  __shared__ double Bs[kEb * kKMajorLd];  // B(k, c) at lds_at<!TB>(k, c)
+  const int64_t T = LOWER ? (int64_t)nrt * (nrt + 1) / 2 : (int64_t)nrt * nct;
+  const int64_t h = blockIdx.x, xcd = h & 7, q8 = T >> 3, rem8 = T & 7;
+  const int64_t b = xcd * q8 + (xcd < rem8 ? xcd : rem8) + (h >> 3);
+  int64_t ti, tj;
+  if (LOWER) {
+    ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    while (ti * (ti + 1) / 2 > b) --ti;
+    tj = b - ti * (ti + 1) / 2;
+  } else {
+    ti = b / nct;
+    tj = b - ti * nct;
+  }
+  const int64_t R = kEb * ti, Cc = kEb * tj;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = 32 * (wave >> 1), c0 = 32 * (wave & 1);
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  constexpr int kPer = kEb * kEb / 256;
+  double av[kPer], bv[kPer];
+  auto load = [&](int64_t kc) {
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it;
+      const int x = e / kEb, y = e % kEb;  // consecutive threads: consecutive y
+      {
+        const int r = TA ? y : x, k = TA ? x : y;
+        const bool ok = kc + k < kk && R + r < m;
+        av[it] = ok ? (TA ? A[(kc + k) * lda + R + r] : A[(R + r) * lda + kc + k]) : 0.0;
+      }
+      {
+        const int c = TB ? x : y, k = TB ? y : x;
+        const bool ok = kc + k < kk && Cc + c < nn;
+        bv[it] = ok ? (TB ? B[(Cc + c) * ldb + kc + k] : B[(kc + k) * ldb + Cc + c]) : 0.0;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = (int)threadIdx.x + 256 * it;
+      const int x = e / kEb, y = e % kEb;
+      As[TA ? lds_at<true>(x, y) : lds_at<false>(y, x)] = av[it];
+      Bs[TB ? lds_at<false>(y, x) : lds_at<true>(x, y)] = bv[it];
+    }
+  };
+  load(0);
+  for (int64_t kc = 0; kc < kk; kc += kEb) {
+    if (kc > 0) __syncthreads();  // every wave is done with the previous chunk
+    store();
+    __syncthreads();
+    if (kc + kEb < kk) load(kc + kEb);
+#pragma unroll 4
+    for (int k = 0; k < kEb; k += 4) {
+      const double a0 = As[lds_at<TA>(k + lk, r0 + lr)], a1 = As[lds_at<TA>(k + lk, r0 + 16 + lr)];
+      const double b0 = Bs[lds_at<!TB>(k + lk, c0 + lr)], b1 = Bs[lds_at<!TB>(k + lk, c0 + 16 + lr)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = R + r0 + 16 * rb + lk + 4 * i, col = Cc + c0 + 16 * cb + lr;
+        if (row < m && col < nn) C[row * ldc + col] = acc[rb][cb][i];
+      }
+}
+
 static int ntiles(int64_t len) { return (int)((len + kEb - 1) / kEb); }
 
 // A = L L^T in place (lower triangle; the diagonal blocks' upper parts are
@@ -400,14 +489,10 @@ __global__ void identity_kernel(double* __restrict__ B, int64_t n) {
 // L^{-T} L^{-1} on the lower triangle, then mirrored.  Both passes are blocked
 // like the factorisation: 64-row blocks update the rest of their 256-row
 // super-block, and the rows beyond it take the whole super-block at once.
-static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st) {
-  identity_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(B, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // The diagonal blocks' inverses, kept for both passes: block bi at Dinv + 64 * 64 * bi.
-  const int64_t nb = (n + kEb - 1) / kEb;
-  trtri_blocks_kernel<<<(unsigned)nb, 256, 0, st>>>(L, n, Dinv);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+// B <- L^{-1} B for B = I on entry (the diagonal blocks' inverses in Dinv):
+// block row i needs columns [0, i0 + 64) only.
+static hipError_t lower_inverse_forward(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st) {
+  hipError_t e = hipSuccess;
   // forward: X_i = L_ii^{-1} B_i on columns [0, i0 + ib); then B_r -= L_ri X_i
   // on the same columns for the rows r of the super-block below block i; after
   // the super-block, the rows below it at once (k = its height, columns
@@ -434,6 +519,18 @@ static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv
       if (e != hipSuccess) return e;
     }
   }
+  return hipSuccess;
+}
+
+static hipError_t inverse_from_cholesky(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st) {
+  identity_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(B, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // The diagonal blocks' inverses, kept for both passes: block bi at Dinv + 64 * 64 * bi.
+  const int64_t nb = (n + kEb - 1) / kEb;
+  trtri_blocks_kernel<<<(unsigned)nb, 256, 0, st>>>(L, n, Dinv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = lower_inverse_forward(L, B, Dinv, n, st)) != hipSuccess) return e;
   // backward, from the last block: Z_i = L_ii^{-T} C_i on columns
   // [0, i0 + ib); then C[R][Cc] -= L[i-block][R]^T Z[i-block][Cc] on the lower
   // tiles of the super-block's rows above block i (their triangle, then the
@@ -705,6 +802,46 @@ int run_exact(const gp_kernel* kern, const double* X, const double* y, int64_t n
       if (!std::isfinite(grad[j])) return fail(GP_ENONFINITE, "gp_exact_mll_and_grad: non-finite gradient");
   }
   return GP_OK;
+}
+
+// ---------------------------------------------------------------- exported dense pieces
+
+hipError_t dense_gemm(bool ta, bool tb, bool lower, int64_t m, int64_t nn, int64_t kk, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || nn <= 0) return hipSuccess;
+  if (lower && m != nn) return hipErrorInvalidValue;
+  const int nrt = ntiles(m), nct = ntiles(nn);
+  const int64_t tiles = lower ? (int64_t)nrt * (nrt + 1) / 2 : (int64_t)nrt * nct;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  const unsigned g = (unsigned)tiles;
+#define GPK_GEMM(TA, TB, LO) gemm_f64_kernel<TA, TB, LO><<<g, 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, nn, kk, nrt, nct)
+  if (lower) {
+    if (ta && tb) GPK_GEMM(true, true, true); else if (ta) GPK_GEMM(true, false, true);
+    else if (tb) GPK_GEMM(false, true, true); else GPK_GEMM(false, false, true);
+  } else {
+    if (ta && tb) GPK_GEMM(true, true, false); else if (ta) GPK_GEMM(true, false, false);
+    else if (tb) GPK_GEMM(false, true, false); else GPK_GEMM(false, false, false);
+  }
+#undef GPK_GEMM
+  return hipGetLastError();
+}
+
+size_t dense_dinv_doubles(int64_t n) { return (size_t)((n + kEb - 1) / kEb) * kEb * kEb; }
+
+hipError_t dense_cholesky(double* A, int64_t n, int* info, double* Dinv, hipStream_t st) {
+  return cholesky(A, n, info, Dinv, st);
+}
+
+// B = L^{-1} (lower triangular, zero above the diagonal) for the lower factor L
+// (row-major n x n, ld n): the forward pass of inverse_from_cholesky.
+hipError_t dense_lower_inverse(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st) {
+  identity_kernel<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(B, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nb = (n + kEb - 1) / kEb;
+  trtri_blocks_kernel<<<(unsigned)nb, 256, 0, st>>>(L, n, Dinv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return lower_inverse_forward(L, B, Dinv, n, st);
 }
 
 }  // namespace gpk

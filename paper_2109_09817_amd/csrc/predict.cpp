@@ -17,6 +17,8 @@ size_t nystrom_ws_bytes(int d, int64_t n, int r);
 size_t nystrom_apply_ws_bytes(int64_t n, int r, int s);
 size_t bcg_ws_bytes(int precision, int d, int64_t n, int r, int s);
 size_t exact_ws_bytes(int d, int64_t n);
+size_t nystrom_chol_ws_bytes(int d, int64_t n, int r);
+size_t bpcg_ws_bytes(int precision, int d, int64_t n, int r, int s);
 
 constexpr int kMaxCache = 4095;  // kc + 1 <= 4096 product columns
 
@@ -177,7 +179,8 @@ extern "C" size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d
                                      int32_t precision) {
   if (n < 1 || d < 1 || d > GP_MAX_D) return 0;
   if (precision != GP_PREC_FP32 && precision != GP_PREC_BF16X3 && precision != GP_PREC_FP64) return 0;
-  if (precision == GP_PREC_FP64 && op != GP_OP_KMM && op != GP_OP_MBCG && op != GP_OP_BCG && op != GP_OP_EXACT)
+  if (precision == GP_PREC_FP64 && op != GP_OP_KMM && op != GP_OP_MBCG && op != GP_OP_BCG && op != GP_OP_EXACT &&
+      op != GP_OP_BPCG && op != GP_OP_NYSTROM_CHOL)
     return 0;
   switch (op) {
     case GP_OP_KMM:
@@ -215,6 +218,12 @@ extern "C" size_t gp_workspace_bytes(int32_t op, int64_t n, int64_t m, int32_t d
       return bcg_ws_bytes(precision, d, n, k, t);
     case GP_OP_EXACT:
       return exact_ws_bytes(d, n);
+    case GP_OP_NYSTROM_CHOL:
+      if (k < 1 || k > 16384 || k > n) return 0;
+      return nystrom_chol_ws_bytes(d, n, k);
+    case GP_OP_BPCG:
+      if (k < 0 || k > 16384 || k > n || t < 1 || t > 64) return 0;
+      return bpcg_ws_bytes(precision, d, n, k, t);
     default:
       return 0;
   }

@@ -91,6 +91,20 @@ hipError_t pivchol_launch_argmax(const double* delta, int64_t n, double* pval, i
 hipError_t pivchol_launch_column(const double* X, int64_t n, const gp_kernel* kern, double* L, double* delta,
                                  const PivState& ps, int m, hipStream_t st);
 
+// Dense FP64 pieces on the matrix cores (exact.hip).  Row-major matrices.
+// C (m x nn, ldc) = A B with A(i, k) = ta ? A[k lda + i] : A[i lda + k] and
+// B(k, j) = tb ? B[j ldb + k] : B[k ldb + j]; lower: only the tiles on and
+// below the diagonal (m = nn).
+hipError_t dense_gemm(bool ta, bool tb, bool lower, int64_t m, int64_t nn, int64_t kk, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t st);
+// Doubles of the diagonal-block scratch of the two routines below.
+size_t dense_dinv_doubles(int64_t n);
+// In-place lower Cholesky factor of the symmetric n x n A (lower triangle read);
+// *info (device, zeroed by the caller) receives 1 + the first non-positive pivot.
+hipError_t dense_cholesky(double* A, int64_t n, int* info, double* Dinv, hipStream_t st);
+// B = L^{-1} for a lower Cholesky factor L (zero above the diagonal).
+hipError_t dense_lower_inverse(const double* L, double* B, double* Dinv, int64_t n, hipStream_t st);
+
 // Host: e_1^T log(T) e_1 for the Lanczos tridiagonal of CG coefficients
 // (alpha[j*stride], beta[j*stride], j < J).  Returns false if T is not
 // positive definite or the eigen-iteration fails.

@@ -351,6 +351,55 @@ def bcg(kern: Kernel, X: torch.Tensor, B: torch.Tensor, max_iter: int, tol: floa
     return BcgResult(W, int(it.value), rr, rc)
 
 
+@dataclasses.dataclass
+class NystromChol:
+    """AltBBMM preconditioner at large rank: P^{-1} = sigma^{-2} (I - E E^T), E (r, n) = n x r column-major."""
+
+    E: torch.Tensor
+    landmarks: np.ndarray
+    noise: float
+
+    @property
+    def rank(self) -> int:
+        return self.E.shape[0]
+
+
+def nystrom_chol_precond(kern: Kernel, X: torch.Tensor, landmarks) -> NystromChol:
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    M = np.ascontiguousarray(np.asarray(landmarks, dtype=np.int64))
+    r = M.shape[0]
+    E = torch.empty((r, n), dtype=torch.float64, device=X.device)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM_CHOL, n, 0, kern.d, 0, r, _lib.GP_PREC_FP64), X.device)
+    ks, _keep = kern.struct()
+    _lib.check(lib.gp_nystrom_chol_precond(C.byref(ks), X.data_ptr(), n, M.ctypes.data_as(C.POINTER(C.c_int64)), r,
+                                           E.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return NystromChol(E, M, kern.noise)
+
+
+def bpcg(kern: Kernel, X: torch.Tensor, B: torch.Tensor, max_iter: int, tol: float,
+         pc: Optional[NystromChol] = None, precision="bf16x3") -> BcgResult:
+    """AltBBMM: block preconditioned CG on K_hat W = B with P^{-1} = sigma^{-2} (I - E E^T) (or P = I)."""
+    lib = _lib.load()
+    n = X.shape[0]
+    _need(X, "X", (n, kern.d))
+    s = B.shape[0]
+    _need(B, "B", (s, n))
+    r = 0 if pc is None else pc.rank
+    W = torch.empty_like(B)
+    p = _prec(precision)
+    ws = workspace(lib.gp_workspace_bytes(_lib.GP_OP_BPCG, n, 0, kern.d, s, r, p), X.device)
+    it = C.c_int32(0)
+    rr = np.zeros(s)
+    ks, _keep = kern.struct()
+    rc = _lib.check(lib.gp_bpcg(C.byref(ks), p, X.data_ptr(), n, _ptr(None if pc is None else pc.E), r, B.data_ptr(),
+                                n, s, max_iter, tol, W.data_ptr(), n, C.byref(it),
+                                rr.ctypes.data_as(C.POINTER(C.c_double)), ws.data_ptr(), ws.numel(),
+                                _stream(X.device)))
+    return BcgResult(W, int(it.value), rr, rc)
+
+
 def lanczos_cache(kern: Kernel, X: torch.Tensor, y: torch.Tensor, kc: int, precision="bf16x3"):
     """Variance cache R (kc, n) with R R^T ~ K_hat^{-1} on the Krylov space of y; returns (R, rank)."""
     lib = _lib.load()

@@ -129,6 +129,7 @@ class Server:
         self.inflight = {}  # slot -> (requests, offsets, rows, bytes)
         self.used = 0
         self.stop = False
+        self.error = None  # what stopped the scheduler thread, if anything did
         self.next_id = 0
         self.completed = 0
         self.batches = 0
@@ -156,10 +157,13 @@ class Server:
         return fut
 
     def close(self):
+        """Drain the queue and stop; raises what stopped the scheduler, if it died."""
         with self.cv:
             self.stop = True
             self.cv.notify()
         self.thread.join()
+        if self.error is not None:
+            raise RuntimeError("prediction server stopped on a scheduler failure") from self.error
 
     # -- scheduler
     def _complete(self, slot):
@@ -218,13 +222,13 @@ class Server:
         except BaseException as e:  # the scheduler cannot go on: no client may wait forever
             with self.cv:
                 self.stop = True
+                self.error = e
                 pending = [r for reqs, _, _, _ in self.inflight.values() for r in reqs] + list(self.queue)
                 self.inflight.clear()
                 self.queue.clear()
             for r in pending:
                 if not r.future.done():
                     r.future.set_exception(RuntimeError(f"prediction server stopped: {e!r}"))
-            raise
 
     def _schedule(self):
         while True:

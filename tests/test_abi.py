@@ -160,6 +160,39 @@ def test_altbbmm_entry_points_validate_on_the_host(lib):
     assert lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM, 1000, 0, 48, 0, 1025, 1) == 0
 
 
+def test_large_rank_altbbmm_entry_points_validate_on_the_host(lib):
+    from paper_2109_09817_amd import _lib
+    k, keep = _kernel()
+    fake = 4096  # never dereferenced: validation fails first
+    M = np.array([0, 3, 3], dtype=np.int64)
+    Mp = M.ctypes.data_as(C.POINTER(C.c_int64))
+    assert lib.gp_nystrom_chol_precond(C.byref(k), fake, 10, Mp, 3, fake, None, 0, None) == _lib.GP_EINVAL
+    assert b"repeated" in lib.gp_last_error()
+    M2 = np.array([0, 1, 2], dtype=np.int64)
+    M2p = M2.ctypes.data_as(C.POINTER(C.c_int64))
+    assert lib.gp_nystrom_chol_precond(C.byref(k), fake, 10, M2p, 3, None, None, 0, None) == _lib.GP_EINVAL
+    assert lib.gp_nystrom_chol_precond(C.byref(k), fake, 10, M2p, 3, fake, None, 0, None) == _lib.GP_EWORKSPACE
+    k0, keep0 = _kernel(noise=0.0)
+    assert lib.gp_nystrom_chol_precond(C.byref(k0), fake, 10, M2p, 3, fake, None, 0, None) == _lib.GP_EINVAL
+    it = C.c_int32(0)
+    rr = np.zeros(64)
+    rrp = rr.ctypes.data_as(C.POINTER(C.c_double))
+
+    def call(prec=1, E=None, r=0, s=2, ldb=10, mi=5, tol=1e-6):
+        return lib.gp_bpcg(C.byref(k), prec, fake, 10, E, r, fake, ldb, s, mi, tol, fake, 10, C.byref(it), rrp,
+                           None, 0, None)
+
+    assert call(s=0) == _lib.GP_EINVAL and call(s=65) == _lib.GP_EINVAL
+    assert call(ldb=9) == _lib.GP_EINVAL and call(mi=0) == _lib.GP_EINVAL and call(tol=-1.0) == _lib.GP_EINVAL
+    assert call(r=3) == _lib.GP_EINVAL  # r > 0 without E
+    assert call(prec=5) == _lib.GP_EINVAL
+    assert call() == _lib.GP_EWORKSPACE
+    assert lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM_CHOL, 131072, 0, 48, 0, 10000, 1) > 131072 * 10000 * 8
+    assert lib.gp_workspace_bytes(_lib.GP_OP_NYSTROM_CHOL, 1000, 0, 48, 0, 16385, 1) == 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_BPCG, 131072, 0, 48, 50, 10000, 2) > 0
+    assert lib.gp_workspace_bytes(_lib.GP_OP_BPCG, 1000, 0, 48, 65, 0, 1) == 0
+
+
 def test_fp64_products_are_limited_to_the_solves(lib):
     from paper_2109_09817_amd import _lib
     k, keep = _kernel()

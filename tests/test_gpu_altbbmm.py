@@ -123,3 +123,103 @@ def test_bcg_reports_no_convergence():
     B = np.column_stack([y, np.random.default_rng(1).standard_normal((n, 3))])
     res = gp.bcg(_gk(th), dev(X), dev(B.T), 2, 1e-12, precision="fp32")
     assert res.status == _lib.GP_WNOCONV and res.iters == 2
+
+
+# ---------------------------------------------------------------- large rank (Cholesky factor form)
+
+@pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
+@pytest.mark.parametrize("n,r", [(1500, 37), (1500, 300), (4000, 2048)])
+def test_nystrom_chol_matches_oracle(kind, n, r):
+    """E of the large-rank preconditioner: sigma^{-2} (V - E E^T V) against the oracle's dense
+    P^{-1} V, P = K_XM (K_MM + delta I)^{-1} K_MX + sigma^2 I (r = 2048 is beyond the spectral
+    form's limit of 1024)."""
+    from paper_2109_09817_amd import gp
+    X, y, th = _problem(n, kind=kind)
+    M = _landmarks(n, r, 17)
+    pc = gp.nystrom_chol_precond(_gk(th), dev(X), M)
+    E = host(pc.E).T  # n x r
+    P_ref = ab.nystrom_matrix_jitter(X, th, M)
+    V = np.random.default_rng(4).standard_normal((n, 5))
+    got = (V - E @ (E.T @ V)) / th.noise
+    ref = np.linalg.solve(P_ref, V)
+    condP = np.linalg.cond(P_ref)
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    ee = np.linalg.eigvalsh(E.T @ E)
+    log(f"nystrom chol kind={kind} n={n} r={r}: P^-1 V err {e:.1e} (cond P {condP:.1e}); "
+        f"eig(E^T E) in [{ee.min():.2e}, {ee.max():.6f}]")
+    assert ee.max() < 1.0  # P^{-1} as applied is positive definite
+    assert e <= max(1e-10, 1e-14 * condP)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+@pytest.mark.parametrize("r", [0, 120])
+def test_bpcg_matches_oracle(prec, r):
+    from paper_2109_09817_amd import gp
+    n, s = 1200, 8
+    X, y, th = _problem(n, seed=1)
+    rng = np.random.default_rng(5)
+    B = np.column_stack([y, rng.standard_normal((n, s - 1))])
+    M = _landmarks(n, r, 9) if r else None
+    Kh = ok.khat(X, th)
+    ref = np.linalg.solve(Kh, B)
+    if r:
+        P_ref = ab.nystrom_matrix_jitter(X, th, M)
+        o = ab.block_pcg(lambda D: Kh @ D, B, lambda R: np.linalg.solve(P_ref, R), 1e-6, 400)
+    else:
+        o = ab.block_pcg(lambda D: Kh @ D, B, lambda R: R.copy(), 1e-6, 400)
+    pc = gp.nystrom_chol_precond(_gk(th), dev(X), M) if r else None
+    res = gp.bpcg(_gk(th), dev(X), dev(B.T), 400, 1e-6, pc=pc, precision=prec)
+    W = host(res.W).T
+    ev = np.linalg.eigvalsh(Kh)
+    kappa = ev[-1] / ev[0]
+    eps = {"fp32": 2e-6, "bf16x3": 3e-5, "fp64": 1e-15}[prec]
+    err = np.linalg.norm(W - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    bound = max(1e-5, 10 * kappa * max(1e-6, eps))
+    true_res = np.linalg.norm(Kh @ W - B, axis=0) / np.linalg.norm(B, axis=0)
+    log(f"bpcg {prec} r={r}: iters gpu {res.iters} oracle {o['iters']}, relres max {res.relres.max():.1e}, "
+        f"true residual max {true_res.max():.1e}, solution err max {err.max():.1e} (kappa {kappa:.1e})")
+    assert res.status == 0
+    assert np.all(res.relres <= 1e-6)
+    assert err.max() <= bound
+    assert res.iters <= 2 * o["iters"] + 5
+    if prec == "fp64":
+        # FP64 products: the same recurrence as the oracle's, iteration for iteration
+        assert abs(res.iters - o["iters"]) <= 1
+        assert true_res.max() <= 1e-5
+    if r:
+        plain = ab.block_pcg(lambda D: Kh @ D, B, lambda R: R.copy(), 1e-6, 400)
+        assert o["iters"] < plain["iters"]
+
+
+def test_bpcg_at_rank_beyond_the_spectral_form():
+    """r = 2048 landmarks on n = 4000 rows of the ill-conditioned variant, FP64 products: the
+    preconditioner captures most of the spectrum, and the solve matches the dense one."""
+    from paper_2109_09817_amd import gp
+    n, s, r = 4000, 6, 2048
+    X, y, th = _problem(n, seed=6)
+    rng = np.random.default_rng(8)
+    B = np.column_stack([y, rng.standard_normal((n, s - 1))])
+    M = _landmarks(n, r, 19)
+    pc = gp.nystrom_chol_precond(_gk(th), dev(X), M)
+    res = gp.bpcg(_gk(th), dev(X), dev(B.T), 300, 1e-8, pc=pc, precision="fp64")
+    plain = gp.bpcg(_gk(th), dev(X), dev(B.T), 300, 1e-8, precision="fp64")
+    Kh = ok.khat(X, th)
+    ref = np.linalg.solve(Kh, B)
+    W = host(res.W).T
+    err = np.linalg.norm(W - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    ev = np.linalg.eigvalsh(Kh)
+    kappa = ev[-1] / ev[0]
+    log(f"bpcg r={r} n={n}: {res.iters} iterations (unpreconditioned {plain.iters}), solution err {err.max():.1e} "
+        f"(kappa {kappa:.1e})")
+    assert res.status == 0 and plain.status == 0
+    assert res.iters < plain.iters
+    assert err.max() <= max(1e-6, 1e-8 * kappa * 10)
+
+
+def test_bpcg_reports_no_convergence():
+    from paper_2109_09817_amd import _lib, gp
+    n = 600
+    X, y, th = _problem(n, seed=3)
+    B = np.column_stack([y, np.random.default_rng(1).standard_normal((n, 3))])
+    res = gp.bpcg(_gk(th), dev(X), dev(B.T), 2, 1e-12, precision="fp32")
+    assert res.status == _lib.GP_WNOCONV and res.iters == 2

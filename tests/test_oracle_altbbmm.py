@@ -115,3 +115,78 @@ def test_truncated_nystrom_keeps_the_bounds_and_matches_when_nothing_is_dropped(
     assert np.linalg.eigvalsh(K - Q).min() >= -1e-9
     S = ab.inv_sqrt(P)
     assert np.linalg.eigvalsh(S @ ok.khat(X2, th) @ S).min() >= 1 - 1e-7
+
+
+def test_block_pcg_without_preconditioner_is_block_cg():
+    rng = np.random.default_rng(11)
+    A = _spd(70, rng, 1e2)
+    B = rng.standard_normal((70, 5))
+    a = ab.block_cg(lambda D: A @ D, B, 1e-10, 200)
+    b = ab.block_pcg(lambda D: A @ D, B, lambda R: R.copy(), 1e-10, 200)
+    assert a["iters"] == b["iters"]
+    np.testing.assert_allclose(b["W"], a["X"], rtol=0, atol=1e-10 * np.abs(a["X"]).max())
+    np.testing.assert_allclose(b["relres_hist"][:5], a["relres_hist"][:5], rtol=1e-8)
+
+
+def test_block_pcg_is_block_cg_on_the_symmetric_system():
+    """Left preconditioning with P^{-1} and block CG on P^{-1/2} A P^{-1/2} give the same iterates
+    (W = P^{-1/2} X) and the same residual norms sqrt(r^T P^{-1} r) = ||P^{-1/2} r||."""
+    rng = np.random.default_rng(12)
+    n, s = 90, 4
+    A = _spd(n, rng, 1e4)
+    P = _spd(n, rng, 1e2)
+    B = rng.standard_normal((n, s))
+    S = ab.inv_sqrt(P)
+    sym = ab.block_cg(lambda D: S @ (A @ (S @ D)), S @ B, 1e-9, 300)
+    left = ab.block_pcg(lambda D: A @ D, B, lambda R: np.linalg.solve(P, R), 1e-9, 300)
+    # equal in exact arithmetic; rounding separates the two Krylov bases only late in the run
+    k = 6
+    np.testing.assert_allclose(left["relres_hist"][:k], sym["relres_hist"][:k], rtol=1e-7)
+    for j in range(k):
+        np.testing.assert_allclose(left["alphas"][j], sym["alphas"][j], rtol=1e-6, atol=1e-9)
+    assert abs(left["iters"] - sym["iters"]) <= 0.1 * sym["iters"]
+    ref = np.linalg.solve(A, B)
+    for W in (left["W"], S @ sym["X"]):
+        assert np.max(np.abs(W - ref)) <= 1e-9 * np.linalg.cond(A) * np.abs(ref).max()
+
+
+def test_block_pcg_reaches_the_dense_solve():
+    X, th, rng = _problem(n=220, d=3, noise=1e-3)
+    th = ok.Theta(th.ell * 3.0, th.sf, th.noise)  # correlated: an ill-conditioned K_hat
+    Kh = ok.khat(X, th)
+    B = rng.standard_normal((220, 6))
+    M = np.sort(rng.choice(220, 40, replace=False))
+    P = ab.nystrom_matrix_jitter(X, th, M)
+    plain = ab.block_pcg(lambda D: Kh @ D, B, lambda R: R.copy(), 1e-10, 500)
+    pre = ab.block_pcg(lambda D: Kh @ D, B, lambda R: np.linalg.solve(P, R), 1e-10, 500)
+    ref = np.linalg.solve(Kh, B)
+    kappa = np.linalg.cond(Kh)
+    for r in (plain, pre):
+        assert np.all(r["relres"] <= 1e-10)
+        assert np.max(np.abs(r["W"] - ref)) <= 1e-9 * kappa * np.abs(ref).max()
+    assert pre["iters"] < plain["iters"]
+
+
+def test_jittered_nystrom_bounds_and_limits():
+    """delta -> 0 recovers the plain Nystrom matrix; with delta > 0 the approximation stays below K
+    (K_hat - P positive semidefinite) and above sigma^2 I; the large-rank factor identity
+    P^{-1} = sigma^{-2} (I - E E^T), E = F L_G^{-T}, F = K_XM L_M^{-T}, holds."""
+    X, th, rng = _problem(n=150, d=4, noise=1e-2)
+    M = np.sort(rng.choice(150, 30, replace=False))
+    P0 = ab.nystrom_matrix(X, th, M)
+    np.testing.assert_allclose(ab.nystrom_matrix_jitter(X, th, M, 0.0), P0, rtol=0, atol=1e-10)
+    P = ab.nystrom_matrix_jitter(X, th, M, 1e-4)
+    Kh = ok.khat(X, th)
+    assert np.linalg.eigvalsh(Kh - P).min() >= -1e-10
+    assert np.linalg.eigvalsh(P).min() >= th.noise * (1 - 1e-10)
+    assert np.linalg.eigvalsh(P0 - P).min() >= -1e-10  # a larger shift gives a smaller approximation
+    # the factor form of the inverse
+    KXM = ok.kernel(X, X[M], th)
+    delta = 1e-4 * M.shape[0] * th.sf
+    LM = np.linalg.cholesky(KXM[M] + delta * np.eye(M.shape[0]))
+    F = np.linalg.solve(LM, KXM.T).T
+    LG = np.linalg.cholesky(F.T @ F + th.noise * np.eye(M.shape[0]))
+    E = np.linalg.solve(LG, F.T).T
+    Pinv = (np.eye(150) - E @ E.T) / th.noise
+    np.testing.assert_allclose(Pinv @ P, np.eye(150), rtol=0, atol=1e-9)
+    assert np.linalg.eigvalsh(E.T @ E).max() < 1.0

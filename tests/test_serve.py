@@ -135,6 +135,9 @@ def test_scheduler_failure_resolves_every_pending_request():
     assert not srv.thread.is_alive()
     late = srv.submit(np.ones((1, 2)))
     assert isinstance(late.exception(timeout=1), RuntimeError)
+    with pytest.raises(RuntimeError) as ei:
+        srv.close()
+    assert isinstance(ei.value.__cause__, MemoryError)
 
 
 def test_memory_budget_limits_inflight_batches():
