@@ -61,7 +61,7 @@ def _definition(text, name):
 
 # The sweep kernel and everything it executes: its source text decides whether recorded counters apply.
 SWEEP_SOURCES = [("paper_2109_09817_amd/csrc/kmm.hip", ["profile", "NAOf", "ChunkUnits", "sweep_bf16x3_kernel"]),
-                 ("paper_2109_09817_amd/csrc/mfma_bf16.h", ["split_bf16x8", "vperm"])]
+                 ("paper_2109_09817_amd/csrc/mfma_bf16.h", ["split_bf16x8", "mfma_dist", "vperm"])]
 
 
 def sweep_source_digest():
@@ -99,7 +99,8 @@ def main():
     ap.add_argument("--no-altbbmm", action="store_true", help="skip the AltBBMM solve")
     ap.add_argument("--no-protocol", action="store_true",
                     help="skip the AltBBMM protocol (exact GP on 50 molecules, then the FP64 full-set solve)")
-    ap.add_argument("--serve-seconds", type=float, default=60.0, help="measured Poisson serving time")
+    ap.add_argument("--serve-requests", type=int, default=12000,
+                    help="measured window: this many Poisson arrivals at --serve-rate (12,000 at 200/s: about 60 s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="Poisson load before the measured window")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--profile-kmm", type=int, default=0, metavar="K",
@@ -753,8 +754,8 @@ def serve_leg(args, gp, synth, torch, dev, np):
     ex = GpuExecutor(model, slots=4, max_rows=2048)
     srv = Server(ex, d=p.X.shape[1], hbm_budget=2 << 30)
 
-    def drive(duration, seed):
-        reqs = synth.request_stream(args.serve_rate, duration, seed=seed)
+    def drive(duration, seed, count=None):
+        reqs = synth.request_stream(args.serve_rate, duration, seed=seed, count=count)
         payload = [synth.query_molecule("c5", m, seed=s) for (_, m, s) in reqs]
         futs = []
         start = time.perf_counter()
@@ -768,12 +769,12 @@ def serve_leg(args, gp, synth, torch, dev, np):
 
     warm, _ = drive(args.serve_warmup, seed=4) if args.serve_warmup > 0 else ([], 0.0)
     log(f"serving warm-up: {len(warm)} requests over {args.serve_warmup:.0f} s")
-    results, wall = drive(args.serve_seconds, seed=5)
+    results, wall = drive(None, seed=5, count=args.serve_requests)
     srv.close()
     summ = latency_summary(results, wall)
     summ.update({"model_n": p.X.shape[0], "model": "generating hyperparameters of the n = 262,144 serving model",
                  "cache_rank": kc, "cache_precision": "bf16x3", "rate_req_s": args.serve_rate,
-                 "seconds": args.serve_seconds, "warmup_seconds": args.serve_warmup, "warmup_requests": len(warm),
+                 "seconds": wall, "warmup_seconds": args.serve_warmup, "warmup_requests": len(warm),
                  "slots": 4, "hbm_budget_bytes": 2 << 30, "alpha_solve_iters": int(sol.alpha.shape[0]),
                  "alpha_relres": float(sol.relres[0]), "setup_s": {"alpha": t1 - t0, "lanczos_cache": t2 - t1}})
     log(f"serving: p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms, {summ['requests']} requests")

@@ -429,9 +429,9 @@ static GradGeom grad_geom(int precision, int d, int64_t n, int t) {
   return g;
 }
 
-// BF16X3 form: its own four-term distance operands for the mpad rows (>= npad):
-// b-side and a-side fragments and the FP64 norm scratch.
-static size_t dist4_bytes(const GradGeom& g) {
+// BF16X3 form: its own FP16 distance operands for the mpad rows (>= npad), at
+// the sweep's K step count: b-side and a-side fragments and the FP64 norm scratch.
+static size_t dist_bytes(const GradGeom& g) {
   return 2 * align256((size_t)g.mpad * g.ks * 64) + align256((size_t)g.mpad * 8);
 }
 
@@ -439,7 +439,7 @@ size_t grad_ws_bytes(int precision, int d, int64_t n, int t) {
   const GradGeom g = grad_geom(precision, d, n, t);
   if (g.ks < 0 || g.ksc < 0) return 0;
   const int64_t nparts = g.nparts();
-  size_t b = g.mixed ? dist4_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
+  size_t b = g.mixed ? dist_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
   b += align256((size_t)std::max(g.npad, g.mpad) * g.ksc * 64);  // b-side C fragments
   b += align256((size_t)g.mpad * g.ksc * 64);                    // a-side C fragments
   b += align256((size_t)g.npad * g.ncb * 64);                    // form fragments (hi+lo or float4 pairs)
@@ -486,7 +486,7 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   const int d = kern->d;
   const GradGeom g = grad_geom(precision, d, n, t);
   if (g.ks < 0 || g.ksc < 0) return fail(GP_EINVAL, "gp_kmm_grad: unsupported d=%d or t=%d", d, t);
-  const size_t kb = g.mixed ? dist4_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
+  const size_t kb = g.mixed ? dist_bytes(g) : kmm_plan_bytes(precision, d, n, n, true, 1);
   KmmPlan plan;
   if (!g.mixed && !kmm_plan_init(plan, kern, precision, n, n, true, 1, ws, kb))
     return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace too small");
@@ -518,11 +518,11 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
     colmean_final_kernel<<<1, 128, 0, st>>>(rpart, rs.nblk, d, n, mu);
   }
   const unsigned thr = 256;
-  char* x4r = (char*)ws;  // BF16X3 form: [b-side | a-side | norms] at the front of ws
-  char* x4c = x4r + align256((size_t)g.mpad * g.ks * 64);
-  double* x4n = (double*)(x4c + align256((size_t)g.mpad * g.ks * 64));
+  char* dxr = (char*)ws;  // BF16X3 form: [b-side | a-side | norms] at the front of ws
+  char* dxc = dxr + align256((size_t)g.mpad * g.ks * 64);
+  double* dxn = (double*)(dxc + align256((size_t)g.mpad * g.ks * 64));
   if (g.mixed)
-    GPK_HIP(prep_dist4(kern, X, n, g.mpad, g.ks, x4r, x4c, x4n, st));
+    GPK_HIP(prep_dist(kern, X, n, g.mpad, g.ks, dxr, dxc, dxn, st));
   else
     GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
   bool ok = false;
@@ -542,8 +542,8 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
                                                                                    g.nchunks, (bf16x8*)gv);
     GPK_HIP(hipGetLastError());
     GradTriArgs a;
-    a.xr = (const bf16x8*)x4r;
-    a.xc = (const bf16x8*)x4c;
+    a.xr = (const bf16x8*)dxr;
+    a.xc = (const bf16x8*)dxc;
     a.cb = (const bf16x8*)wf;
     a.ca = (const bf16x8*)uf;
     a.gv = (const bf16x8*)gv;

@@ -13,9 +13,10 @@
 // Work unit: a row group of 64 or 128 rows a (4 waves x one or two 16-row
 // blocks, held in registers) against a range of 32-point chunks b at or after the group's own
 // first chunk; pairs with b <= a inside a chunk that straddles a block are
-// masked.  Per (16 rows) x (32 points) tile, on the BF16 matrix cores:
-//   S    = |x~_a - x~_b|^2          (distance, K = 4d + 6: the four products
-//                                    hi.hi + hi.lo + lo.hi + lo.lo and split norms)
+// masked.  Per (16 rows) x (32 points) tile, on the matrix cores:
+//   S    = |x~_a - x~_b|^2          (distance, K = 3d + 6: FP16 hi/lo coordinates
+//                                    centred on the first point, the products
+//                                    hi.hi + hi.lo + lo.hi and the norm digits)
 //   C^s  = [W_b | U_b] . [w U_a | w W_a]^T   (K = 2t, split three ways)
 //   P    = psi(S) C^s, its row sums, and sum k(S) C^s   (registers, FP32)
 //   Q, T = P . [x~_b | x~_b^2]       (2 ceil(d/16) blocks of 16 columns)
@@ -32,8 +33,8 @@ namespace gpk {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct GradTriArgs {
-  const bf16x8* xr;     // b-stream four-term distance fragments (A operand)
-  const bf16x8* xc;     // a-row four-term distance fragments (B operand)
+  const bf16x8* xr;     // b-stream FP16 distance fragments (A operand)
+  const bf16x8* xc;     // a-row FP16 distance fragments (B operand)
   const bf16x8* cb;     // b-stream fragments of [W | U]        (A operand, K = 6t: hi | hi | lo)
   const bf16x8* ca;     // a-row fragments of [w U | w W]       (B operand, K = 6t: hi | lo | hi)
   const bf16x8* gv;     // b-stream fragments of [x~ | x~^2]    (B operand of the forms, hi and lo)
@@ -65,15 +66,15 @@ constexpr int tri_na(int ks, int ksc, int nj) { return ksc <= tri_max_ksc2(ks, n
 // Rows of one row group (a workgroup's register-resident rows).
 constexpr int tri_rows(int ks, int ksc, int nj) { return 16 * kTriWaves * tri_na(ks, ksc, nj); }
 
-// K steps of 32 of the four-term distance operands for d features (K = 4d + 6),
-// rounded up to the instantiated counts; -1 above d = 64.  The zero K padding
-// is exact.
+// K steps of 32 of the distance operands for d features (K = 3d + 6), one
+// instantiated count per number of 16-feature form blocks nj = ceil(d / 16):
+// 2, 4, 5, 7 for nj = 1..4 (each covers the largest d of its nj); -1 above
+// d = 64.  The zero K padding is exact.
 inline int tri_ks_of(int d) {
-  const int need = (4 * d + 6 + 31) / 32;
-  static const int kAvail[] = {2, 4, 5, 7, 9};
-  for (int k : kAvail)
-    if (k >= need) return k;
-  return -1;
+  static const int kByNj[] = {2, 4, 5, 7};
+  if (d < 1 || d > 64) return -1;
+  const int ks = kByNj[(d + 15) / 16 - 1];
+  return ks * 32 >= 3 * d + 6 ? ks : -1;
 }
 
 // Launch one instantiation; false if (ks, nj, ksc) has none.

@@ -143,8 +143,8 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
         for (int ab = 0; ab < NA; ++ab) {
           if (!live[ab]) continue;
-          s0[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0f, A[ab][ks], s0[ab], 0, 0, 0);
-          s1[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1f, A[ab][ks], s1[ab], 0, 0, 0);
+          s0[ab] = mfma_dist(b0f, A[ab][ks], s0[ab]);
+          s1[ab] = mfma_dist(b1f, A[ab][ks], s1[ab]);
         }
       }
       bf16x8 H[NA], L[NA];
@@ -251,19 +251,14 @@ static bool tri_ksc(int ksc, unsigned units, const GradTriArgs& a, hipStream_t s
   }
 }
 
-// (KS, NJ) pairs for d <= 64 with the four-term distance (see tri_ks_of):
-//   d <= 14: (2, 1)   d <= 16: (4, 1)   d <= 30: (4, 2)   d <= 32: (5, 2)
-//   d <= 38: (5, 3)   d <= 48: (7, 3)   d <= 54: (7, 4)   d <= 64: (9, 4)
+// (KS, NJ) pairs for d <= 64 (see tri_ks_of):
+//   d <= 16: (2, 1)   d <= 32: (4, 2)   d <= 48: (5, 3)   d <= 64: (7, 4)
 template <int KIND>
 static bool tri_dispatch(int ks, int nj, int ksc, unsigned units, const GradTriArgs& a, hipStream_t st) {
   if (ks == 2 && nj == 1) return tri_ksc<2, 1, KIND>(ksc, units, a, st);
-  if (ks == 4 && nj == 1) return tri_ksc<4, 1, KIND>(ksc, units, a, st);
   if (ks == 4 && nj == 2) return tri_ksc<4, 2, KIND>(ksc, units, a, st);
-  if (ks == 5 && nj == 2) return tri_ksc<5, 2, KIND>(ksc, units, a, st);
   if (ks == 5 && nj == 3) return tri_ksc<5, 3, KIND>(ksc, units, a, st);
-  if (ks == 7 && nj == 3) return tri_ksc<7, 3, KIND>(ksc, units, a, st);
   if (ks == 7 && nj == 4) return tri_ksc<7, 4, KIND>(ksc, units, a, st);
-  if (ks == 9 && nj == 4) return tri_ksc<9, 4, KIND>(ksc, units, a, st);
   return false;
 }
 

@@ -24,9 +24,12 @@
 // in FP64 by the epilogue as (s_f + sigma^2) V.
 //
 // Two arithmetic forms share this structure:
-//   BF16X3: operands split x = hi + lo in BF16 (round to nearest even), the
-//           three products hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16,
-//           FP32 accumulation; M is split the same way for the second product.
+//   BF16X3: the distance from FP16 hi/lo coordinates (centred on the b
+//           stream's first point) with the three products hi.hi + hi.lo + lo.hi
+//           on v_mfma_f32_16x16x32_f16; M and V split x = hi + lo in BF16 (round
+//           to nearest even, BF16 for its exponent range: kernel values and
+//           vectors span many decades), the same three products on
+//           v_mfma_f32_16x16x32_bf16; FP32 accumulation.
 //   FP32:   v_mfma_f32_16x16x4_f32 for both products; the squared norms
 //           initialise the distance accumulator.
 // Row-independent BF16X3 cross products with many columns (prediction) use a
@@ -77,14 +80,34 @@ __device__ __forceinline__ float profile(float S) {
 __device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(float)x; }
 
 // ---------------------------------------------------------------- preparation
+//
+// Distances of the mixed form.  r^2 = n_a + n_b - 2 x'_a . x'_b runs on the FP16
+// matrix cores with each centred, scaled coordinate x' = (x - c) s split as
+// x' ~ h + l, h = RNE16(x'), l = RNE16(x' - h) (22 significant bits), and the
+// three products h.h + h.l + l.h; n = sum (h + l)^2, so that the dropped l.l
+// leaves an error of 2 l_a . l_b (about 2^-22 |x'|^2, of either sign) instead of a
+// bias.  The centre c is the first point of the b stream (the training points),
+// so the coordinates stay small whatever the data's offset.  FP16 holds
+// |h| <= 32752 (-2h must stay finite): a point with a scaled coordinate beyond
+// that, about 10^4 lengthscales from the centre, gets a NaN norm, and every
+// product involving it is NaN (never silently wrong).  The norms enter the K
+// padding as three FP16 digits against the constants kNormScale (a mixed-radix
+// expansion whose residual is below 1e-9 relative up to n ~ 2e9).
 
-// Squared norm of each prepared point (FP64).  mode 1 (three-term BF16 split):
-// n = sum(h^2 + 2 h l), so that the MFMA distance equals |dx'|^2 - |dl|^2
-// (x' = h + l): its error is relative to the true distance.  mode 2 (four-term
-// split, which also carries l.l): n = sum((h + l)^2), so that the MFMA distance
-// is |dx'|^2 itself.  mode 0 (FP32): n = sum(f^2) with f = fl32(x~).
+constexpr float kNormScale[3] = {32768.f, 16.f, 0.0078125f};  // 2^15, 2^4, 2^-7
+constexpr double kMaxScaled = 32752.0;                      // largest |h| with -2h finite in FP16
+constexpr double kMaxNorm = 65504.0 * 32768.0;              // largest n the top digit holds
+
+__device__ __forceinline__ double f16_round(double x) { return (double)(_Float16)(float)x; }
+
+// Squared norm of each prepared point (FP64).  mode 1 (mixed form): the centred
+// FP16 split above, n = sum (h + l)^2, NaN out of range.  mode 0 (FP32 form):
+// n = sum f^2 with f = fl32(x s), no centring.  ctr: the centre (d values, mode 1);
+// ctr_save (optional): a copy of the centre written by block 0, for the query
+// rows prepared later against the same b stream.
 __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad,
-                                                        int d, Scale sc, int mixed, double* __restrict__ nrm) {
+                                                        int d, Scale sc, int mixed, const double* __restrict__ ctr,
+                                                        double* __restrict__ ctr_save, double* __restrict__ nrm) {
   // Each wave owns 64 consecutive points.  Per slice of 16 features the wave
   // loads the 64 x 16 block of X (each load instruction covers four rows'
   // 128-byte runs), turns every element into its norm term and parks the terms
@@ -96,11 +119,14 @@ __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
   const int fl = lane & 15;
+  if (ctr_save && blockIdx.x == 0)
+    for (int j = threadIdx.x; j < d; j += blockDim.x) ctr_save[j] = ctr[j];
   double s = 0.0;
   if (n > 0) {  // the same for the whole block
     for (int j0 = 0; j0 < d; j0 += kF) {
       const int f = j0 + fl < d ? j0 + fl : d - 1;
       const double scale = sc.s[f];
+      const double c = mixed ? ctr[f] : 0.0;
       double x[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {  // row 4 k + lane / 16 of the wave's 64 (clamped into X)
@@ -110,14 +136,14 @@ __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int i = 4 * k + (lane >> 4);
-        const double v = x[k] * scale;
         double t;
         if (mixed) {
-          const double h = bf16_round(v);
-          const double l = bf16_round(v - h);
-          t = mixed == 2 ? (h + l) * (h + l) : h * h + 2.0 * h * l;
+          const double v = (x[k] - c) * scale;
+          const double h = f16_round(v);
+          const double l = f16_round(v - h);
+          t = __builtin_fabs(v) <= kMaxScaled ? (h + l) * (h + l) : __builtin_nan("");
         } else {
-          const double fv = (float)v;
+          const double fv = (float)(x[k] * scale);
           t = fv * fv;
         }
         term[wave][i][fl] = (r0 + i < n && j0 + fl < d) ? t : 0.0;
@@ -128,18 +154,21 @@ __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict
       __syncthreads();  // the next slice overwrites the terms
     }
   }
+  if (mixed && !(s <= kMaxNorm)) s = __builtin_nan("");
   const int64_t p = r0 + lane;
   if (p < npad) nrm[p] = p < n ? s : 0.0;
 }
 
-// BF16X3 point fragments.  K layout of a prepared point (length 32*KS, zero padded):
-//   row side (b):    [-2h_0..-2h_{d-1}, -2h_0.., -2l_0.., nhi, nmid, nlo, 1, 1, 1, 0..]
-//   column side (a): [  h_0..  h_{d-1},   l_0..,   h_0.., 1, 1, 1, nhi, nmid, nlo, 0..]
-// so that sum_K row*col = -2(h.h + h.l + l.h) + n_b + n_a.  Fragment (blk, ks, lane)
-// holds K = 32 ks + 8 (lane/16) + j, j = 0..7, of point 16 blk + lane%16.
-__global__ void prep_frag_bf16x3_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
-                                        int64_t n, int64_t nblk, int d, int KS, Scale sc,
-                                        bf16x8* __restrict__ xr, bf16x8* __restrict__ xc) {
+// Mixed-form point fragments.  K layout of a prepared point (length 32*KS, zero padded):
+//   row side (b):    [-2h_0..-2h_{d-1}, -2h_0.., -2l_0.., D2, D1, D0, C2, C1, C0, 0..]
+//   column side (a): [  h_0..  h_{d-1},   l_0..,   h_0.., C2, C1, C0, D2, D1, D0, 0..]
+// with C = kNormScale and D the point's norm digits (n = sum_k D_k C_k), so that
+// sum_K row*col = -2(h.h + h.l + l.h) + n_b + n_a.  FP16 values, stored as
+// 16-byte units.  Fragment (blk, ks, lane) holds K = 32 ks + 8 (lane/16) + j,
+// j = 0..7, of point 16 blk + lane%16.
+__global__ void prep_frag_f16x3_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
+                                       const double* __restrict__ ctr, int64_t n, int64_t nblk, int d, int KS,
+                                       Scale sc, bf16x8* __restrict__ xr, bf16x8* __restrict__ xc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nblk * KS * 64) return;
   const int lane = (int)(idx & 63);
@@ -148,97 +177,42 @@ __global__ void prep_frag_bf16x3_kernel(const double* __restrict__ X, const doub
   const int64_t blk = rest / KS;
   const int64_t p = blk * 16 + (lane & 15);
   const int g = lane >> 4;
-  bf16x8 r, c;
-  float nhi = 0.f, nmid = 0.f, nlo = 0.f;
+  f16x8 r, c;
+  double dig[3] = {0.0, 0.0, 0.0};
   if (p < n) {
-    const double nn = nrm[p];
-    nhi = bf16_round(nn);
-    nmid = bf16_round(nn - (double)nhi);
-    nlo = bf16_round(nn - (double)nhi - (double)nmid);
+    double rem = nrm[p];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dig[q] = f16_round(rem * (1.0 / (double)kNormScale[q]));  // powers of two: exact
+      rem -= dig[q] * (double)kNormScale[q];
+    }
   }
   for (int j = 0; j < 8; ++j) {
     const int k = 32 * ks + 8 * g + j;
-    float rv = 0.f, cv = 0.f;
+    double rv = 0.0, cv = 0.0;
     if (p < n) {
       if (k < 3 * d) {
         const int seg = k / d, f = k - seg * d;
-        const double v = X[p * d + f] * sc.s[f];
-        const float h = bf16_round(v);
-        const float l = bf16_round(v - (double)h);
-        rv = -2.f * (seg == 2 ? l : h);
+        const double v = (X[p * d + f] - ctr[f]) * sc.s[f];
+        const double h = f16_round(v);
+        const double l = f16_round(v - h);
+        rv = -2.0 * (seg == 2 ? l : h);
         cv = (seg == 1 ? l : h);
       } else if (k < 3 * d + 3) {
         const int q = k - 3 * d;
-        rv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
-        cv = 1.f;
+        rv = dig[q];
+        cv = kNormScale[q];
       } else if (k < 3 * d + 6) {
         const int q = k - 3 * d - 3;
-        rv = 1.f;
-        cv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
+        rv = kNormScale[q];
+        cv = dig[q];
       }
     }
-    r[j] = (__bf16)rv;
-    c[j] = (__bf16)cv;
+    r[j] = (_Float16)(float)rv;
+    c[j] = (_Float16)(float)cv;
   }
-  if (xr) xr[idx] = r;
-  if (xc) xc[idx] = c;
-}
-
-// Four-term BF16 point fragments (the distances of the hyperparameter-form
-// sweep).  K layout of a prepared point (length 32*KS, zero padded):
-//   row side (b):    [-2h.., -2h.., -2l.., -2l.., nhi, nmid, nlo, 1, 1, 1, 0..]
-//   column side (a): [  h..,   l..,   h..,   l.., 1, 1, 1, nhi, nmid, nlo, 0..]
-// so that sum_K row*col = n_b + n_a - 2 x'_b.x'_a = |x'_a - x'_b|^2 with
-// x' = h + l and n = |x'|^2 (mode 2 of prep_norm_kernel): the dropped l.l
-// product of the three-term form would bias every distance low by about
-// |l_a|^2 + |l_b|^2, a systematic error of ~2^-18 |x~|^2 that does not average
-// out over pairs.  Fragment (blk, ks, lane) holds K = 32 ks + 8 (lane/16) + j of
-// point 16 blk + lane%16.
-__global__ void prep_frag_bf16x4_kernel(const double* __restrict__ X, const double* __restrict__ nrm,
-                                        int64_t n, int64_t nblk, int d, int KS, Scale sc,
-                                        bf16x8* __restrict__ xr, bf16x8* __restrict__ xc) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nblk * KS * 64) return;
-  const int lane = (int)(idx & 63);
-  const int64_t rest = idx >> 6;
-  const int ks = (int)(rest % KS);
-  const int64_t blk = rest / KS;
-  const int64_t p = blk * 16 + (lane & 15);
-  const int g = lane >> 4;
-  bf16x8 r, c;
-  float nhi = 0.f, nmid = 0.f, nlo = 0.f;
-  if (p < n) {
-    const double nn = nrm[p];
-    nhi = bf16_round(nn);
-    nmid = bf16_round(nn - (double)nhi);
-    nlo = bf16_round(nn - (double)nhi - (double)nmid);
-  }
-  for (int j = 0; j < 8; ++j) {
-    const int k = 32 * ks + 8 * g + j;
-    float rv = 0.f, cv = 0.f;
-    if (p < n) {
-      if (k < 4 * d) {
-        const int seg = k / d, f = k - seg * d;
-        const double v = X[p * d + f] * sc.s[f];
-        const float h = bf16_round(v);
-        const float l = bf16_round(v - (double)h);
-        rv = -2.f * (seg < 2 ? h : l);
-        cv = (seg & 1) ? l : h;
-      } else if (k < 4 * d + 3) {
-        const int q = k - 4 * d;
-        rv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
-        cv = 1.f;
-      } else if (k < 4 * d + 6) {
-        const int q = k - 4 * d - 3;
-        rv = 1.f;
-        cv = q == 0 ? nhi : (q == 1 ? nmid : nlo);
-      }
-    }
-    r[j] = (__bf16)rv;
-    c[j] = (__bf16)cv;
-  }
-  if (xr) xr[idx] = r;
-  if (xc) xc[idx] = c;
+  if (xr) xr[idx] = __builtin_bit_cast(bf16x8, r);
+  if (xc) xc[idx] = __builtin_bit_cast(bf16x8, c);
 }
 
 // FP32 point fragments: float4 (blk, q, lane) = f(point 16 blk + lane%16, feature
@@ -437,8 +411,8 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
       f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B0[ks], A[ab][ks], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(B1[ks], A[ab][ks], s1, 0, 0, 0);
+        s0 = mfma_dist(B0[ks], A[ab][ks], s0);
+        s1 = mfma_dist(B1[ks], A[ab][ks], s1);
       }
       f32x8 mv;
 #pragma unroll
@@ -637,8 +611,8 @@ __global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
       f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][ks * 64 + lane], A[ks], s0, 0, 0, 0);
-        s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][(KS + ks) * 64 + lane], A[ks], s1, 0, 0, 0);
+        s0 = mfma_dist(stage[cur][ks * 64 + lane], A[ks], s0);
+        s1 = mfma_dist(stage[cur][(KS + ks) * 64 + lane], A[ks], s1);
       }
       f32x8 mv;
 #pragma unroll
@@ -987,6 +961,7 @@ size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, i
   b += align256((size_t)bpad * 4);                 // nrm_b
   b += align256((size_t)mpad * 4);                 // nrm_a
   b += align256((size_t)bpad * 8);                 // nrm64
+  b += align256((size_t)d * 8);                    // ctr
   b += align256((size_t)npad * ntb * 64 + 64);     // vf
   b += align256(part_bytes_max(npad, mpad, ntb0, !square, ks, precision == GP_PREC_BF16X3));  // partials
   return b;
@@ -1024,20 +999,22 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
   p.nrm_b = (float*)c;  c += align256((size_t)bpad * 4);
   p.nrm_a = (float*)c;  c += align256((size_t)p.mpad * 4);
   p.nrm64 = (double*)c; c += align256((size_t)bpad * 8);
+  p.ctr = (double*)c;   c += align256((size_t)p.d * 8);
   const int ntb_alloc = (p.ntb + nt_launch(p.ntb) - 1) / nt_launch(p.ntb) * nt_launch(p.ntb);
   p.vf = c;  c += align256((size_t)p.npad * ntb_alloc * 64 + 64);
   p.part = (double*)c;
   return true;
 }
 
-// Model buffer: [b-stream fragments | b norms (FP32) | V fragments | FP64 norm scratch of the prepare step].
+// Model buffer: [b-stream fragments | b norms (FP32) | V fragments | centre (d) | FP64 norm scratch of the
+// prepare step].
 size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax) {
   if (precision == GP_PREC_FP64) return 0;  // prediction models use the matrix-core forms
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
   const int64_t npad = round_up(n, 32);
   return align256((size_t)npad * ks * 64) + align256((size_t)npad * 4) + kmm_vfrag_bytes(n, tmax) +
-         align256((size_t)npad * 8);
+         align256((size_t)d * 8) + align256((size_t)npad * 8);
 }
 
 // Query workspace: [row fragments | row norms (FP32) | FP64 norm scratch | partials].
@@ -1074,6 +1051,7 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
   p.xr = c;  c += align256((size_t)p.npad * p.ks * 64);
   p.nrm_b = (float*)c;  c += align256((size_t)p.npad * 4);
   p.vf = c;  c += kmm_vfrag_bytes(n, tmax);
+  p.ctr = (double*)c;  c += align256((size_t)p.d * 8);
   if (m > 0) {
     char* w = (char*)ws;
     p.xc = w;  w += align256((size_t)p.mpad * p.ks * 64);
@@ -1297,19 +1275,22 @@ static Scale make_scale(const gp_kernel* kern) {
   return s;
 }
 
+// ctr: the centre of the mixed form's coordinates (the b stream's first point);
+// ctr_save (optional): where to keep a copy of it for later query rows.
 static hipError_t prep_points(const KmmPlan& p, const Scale& sc, const double* P, int64_t rows,
-                              int64_t rows_pad, void* xr, void* xc, float* nr, float* nc,
-                              hipStream_t st) {
+                              int64_t rows_pad, void* xr, void* xc, float* nr, float* nc, const double* ctr,
+                              double* ctr_save, hipStream_t st) {
   if (!p.nrm64 || !P || (!xr && !xc)) return hipErrorInvalidValue;
   const int mixed = p.precision == GP_PREC_BF16X3;
+  if (mixed && !ctr) return hipErrorInvalidValue;
   const int thr = 256;
-  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(P, rows, rows_pad, p.d, sc,
-                                                                           mixed, p.nrm64);
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(
+      P, rows, rows_pad, p.d, sc, mixed, mixed ? ctr : nullptr, mixed ? ctr_save : nullptr, p.nrm64);
   const int64_t nblk = rows_pad / 16;
   const int64_t total = nblk * p.ks * 64;
   if (mixed) {
-    prep_frag_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
-        P, p.nrm64, rows, nblk, p.d, p.ks, sc, (bf16x8*)xr, (bf16x8*)xc);
+    prep_frag_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
+        P, p.nrm64, ctr, rows, nblk, p.d, p.ks, sc, (bf16x8*)xr, (bf16x8*)xc);
   } else {
     prep_frag_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
         P, p.nrm64, rows, nblk, p.d, p.ks, sc, (f32x4*)xr, (f32x4*)xc, nr, nc);
@@ -1335,7 +1316,7 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
   if (p.square) {
     // one pass gives both sides; rows up to max(npad, mpad) so xc covers mpad
     const int64_t rows_pad = std::max(p.npad, p.mpad);
-    return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, st);
+    return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, X, nullptr, st);
   }
   hipError_t e = kmm_prepare_rows(p, kern, X, st);
   if (e != hipSuccess) return e;
@@ -1344,26 +1325,25 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
 
 hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, hipStream_t st) {
   if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
-  return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, st);
+  return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, X, p.ctr, st);
 }
 
 hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st) {
   if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
-  return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, st);
+  return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, p.ctr, nullptr, st);
 }
 
-int dist4_ksteps(int d) { return d >= 1 && d <= GP_MAX_D ? (4 * d + 6 + 31) / 32 : -1; }
-
-hipError_t prep_dist4(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
-                      void* xc, double* nrm64, hipStream_t st) {
-  if (!X || !nrm64 || (!xr && !xc) || ks < dist4_ksteps(kern->d) || rows_pad % 64 != 0) return hipErrorInvalidValue;
+hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
+                     void* xc, double* nrm64, hipStream_t st) {
+  if (!X || !nrm64 || (!xr && !xc) || ks * 32 < 3 * kern->d + 6 || rows_pad % 64 != 0) return hipErrorInvalidValue;
   const Scale sc = make_scale(kern);
   const int thr = 256;
-  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(X, n, rows_pad, kern->d, sc, 2, nrm64);
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(X, n, rows_pad, kern->d, sc, 1, X,
+                                                                           nullptr, nrm64);
   const int64_t nblk = rows_pad / 16;
   const int64_t total = nblk * ks * 64;
-  prep_frag_bf16x4_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(X, nrm64, n, nblk, kern->d, ks, sc,
-                                                                              (bf16x8*)xr, (bf16x8*)xc);
+  prep_frag_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(X, nrm64, X, n, nblk, kern->d, ks, sc,
+                                                                             (bf16x8*)xr, (bf16x8*)xc);
   return hipGetLastError();
 }
 

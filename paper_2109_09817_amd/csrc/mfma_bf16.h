@@ -10,6 +10,7 @@
 namespace gpk {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
 
@@ -66,6 +67,14 @@ __device__ __forceinline__ void split_bf16x8_dot2(const f32x8& m, bf16x8& H, bf1
     L[2 * p] = l[0];
     L[2 * p + 1] = l[1];
   }
+}
+
+// Distance tile on the matrix cores: the point operands are FP16 (see the
+// preparation of the point fragments) and travel through registers and LDS as
+// 16-byte units of the BF16 vector type; they are reinterpreted, not converted.
+__device__ __forceinline__ f32x4 mfma_dist(const bf16x8& b, const bf16x8& a, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, b), __builtin_bit_cast(f16x8, a), c, 0,
+                                                0, 0);
 }
 
 // K position -> point of a 32-point chunk, for an operand built from the two

@@ -218,15 +218,16 @@ def query_molecule(cfg_name: str, rows: int, seed: int) -> np.ndarray:
     return mu[c] + r.standard_normal((rows, cfg.d))
 
 
-def request_stream(rate: float, duration: float, seed: int, lo: int = 10, hi: int = 300):
-    """Poisson arrivals: (arrival_time_s, rows, request_seed) tuples."""
+def request_stream(rate: float, duration: float, seed: int, lo: int = 10, hi: int = 300, count=None):
+    """Poisson arrivals: (arrival_time_s, rows, request_seed) tuples, those before `duration`
+    seconds, or exactly `count` of them when a count is given (duration then unused)."""
     r = np.random.default_rng(np.random.SeedSequence([int(seed), 13]))
     t = 0.0
     out = []
     i = 0
     while True:
         t += r.exponential(1.0 / rate)
-        if t >= duration:
+        if (count is None and t >= duration) or (count is not None and i >= count):
             break
         out.append((t, int(r.integers(lo, hi + 1)), int(seed) * 1_000_003 + i))
         i += 1

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 # Relative error per vector ||got - ref|| / ||ref|| (the 1e-4 target; FP32 is held tighter).
 TOL = {"fp32": 2e-6, "bf16x3": 1e-4}
 # The same bound on the off-diagonal part s_f M V alone (K_hat V minus its exact diagonal).
-TOL_OFF = {"fp32": 2e-5, "bf16x3": 2e-4}
+TOL_OFF = {"fp32": 2e-5, "bf16x3": 1e-4}
 
 
 def _run(kern_np, X, V, prec, Z=None):
@@ -162,12 +162,14 @@ def test_repeat_runs_are_bitwise_identical():
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,nrows", [("c2", 65536), ("c3d", 131072), ("c3o", 917504)])
-def test_full_size_sampled_rows(name, nrows):
-    # Full-size products (the launch configuration the benchmark times), checked on sampled rows.
+@pytest.mark.parametrize("name,nrows,cond", [("c2", 65536, True), ("c3d", 131072, True), ("c3o", 917504, True),
+                                             ("c3o", 917504, False)])
+def test_full_size_sampled_rows(name, nrows, cond):
+    # Full-size products (the launch configuration the benchmark times), checked on sampled rows; the
+    # N = 917,504 model also as configured (the data the benchmark runs).
     import torch
     from paper_2109_09817_amd import gp
-    p = synth.make_problem(name, n=nrows, cond_variant=True)
+    p = synth.make_problem(name, n=nrows, cond_variant=cond)
     th = ok.Theta(p.ell, p.sf, p.noise)
     t = 16
     V = synth.random_block(nrows, t, 1)
@@ -183,7 +185,7 @@ def test_full_size_sampled_rows(name, nrows):
         err = col_rel_err(got, ref)
         diag = (th.sf + th.noise) * V[:, rows]
         err_off = col_rel_err(got - diag, ref - diag)
-        print(f"{name} n={nrows} {prec}: err={err:.3e} off={err_off:.3e}", file=sys.stderr, flush=True)
+        print(f"{name} n={nrows} cond={cond} {prec}: err={err:.3e} off={err_off:.3e}", file=sys.stderr, flush=True)
         assert err <= TOL[prec]
         assert err_off <= TOL_OFF[prec]
         del out
@@ -259,3 +261,38 @@ def test_mid_size_square_products_match_oracle(n, d, t, kind):
     assert err <= TOL["bf16x3"]
     assert err_off <= TOL_OFF["bf16x3"]
     np.testing.assert_array_equal(got, again)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_products_do_not_depend_on_an_offset_of_the_data(prec):
+    """The kernel depends on differences only.  The mixed form centres its FP16 coordinates on the
+    first training point, so shifting every point (training and query) by 10^4 lengthscales leaves
+    its results at the unshifted accuracy; the FP32 form's norms are not centred and are checked
+    only at a small offset."""
+    n, d, t, m = 3000, 48, 9, 155
+    X, th, V = _case(n, d, t, True, seed=19)
+    Z = synth.query_molecule("c2", m, seed=4)[:, :d]
+    shift = (1e4 if prec == "bf16x3" else 1.0) * th.ell * np.random.default_rng(2).choice([-1.0, 1.0], d)
+    ref = ok.khat_matmul(X, th, V.T).T
+    refc = ok.cross_matmul(Z, X, th, V.T).T
+    got = _run(th, X + shift, V, prec)
+    gotc = _run(th, X + shift, V, prec, Z=Z + shift)
+    diag = (th.sf + th.noise) * V
+    err_off = col_rel_err(got - diag, ref - diag)
+    errc = float(np.linalg.norm(gotc - refc) / np.linalg.norm(refc))
+    print(f"offset {prec}: square off-diagonal err {err_off:.3e}, cross err {errc:.3e}", file=sys.stderr, flush=True)
+    assert err_off <= TOL_OFF[prec] and errc <= TOL_OFF[prec]
+
+
+def test_mixed_form_out_of_range_coordinates_give_nan():
+    """A training point whose scaled coordinate lies beyond the FP16 range of the mixed form's distance
+    (about 10^4 lengthscales from the first point) makes the product NaN rather than silently wrong;
+    the FP32 form still computes it."""
+    n, d, t = 700, 16, 3
+    X, th, V = _case(n, d, t, True, seed=23)
+    X = X.copy()
+    X[n // 2, 3] += 1e5 * th.ell[3]
+    got = _run(th, X, V, "bf16x3")
+    assert np.all(np.isnan(got))
+    ref = ok.khat_matmul(X, th, V.T).T
+    assert col_rel_err(_run(th, X, V, "fp32"), ref) <= TOL["fp32"]
