@@ -135,16 +135,60 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
         s1[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
       // distance tiles of the NA blocks, one staged K step at a time (each LDS
-      // read feeds NA MFMAs; only two b-side fragments are live at once)
+      // read feeds NA MFMAs); the fragments of step ks + 1 are read while the
+      // MFMAs of step ks run
+      bf16x8 b0f = stage[cur][lane];
+      bf16x8 b1f = stage[cur][KS * 64 + lane];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 b0f = stage[cur][ks * 64 + lane];
-        const bf16x8 b1f = stage[cur][(KS + ks) * 64 + lane];
+        bf16x8 n0f, n1f;
+        if (ks + 1 < KS) {
+          n0f = stage[cur][(ks + 1) * 64 + lane];
+          n1f = stage[cur][(KS + ks + 1) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ab = 0; ab < NA; ++ab) {
           if (!live[ab]) continue;
           s0[ab] = mfma_dist(b0f, A[ab][ks], s0[ab]);
           s1[ab] = mfma_dist(b1f, A[ab][ks], s1[ab]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + 1 < KS) {
+          b0f = n0f;
+          b1f = n1f;
+        }
+      }
+      // C^s tiles of the NA blocks, one staged K step at a time, the next
+      // step's fragments read while these MFMAs run
+      f32x4 q0a[NA], q1a[NA];
+#pragma unroll
+      for (int ab = 0; ab < NA; ++ab) {
+        q0a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+        q1a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      {
+        bf16x8 c0f = stage[cur][TC::kDist + lane];
+        bf16x8 c1f = stage[cur][TC::kDist + KSC * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < KSC; ++q) {
+          bf16x8 d0f, d1f;
+          if (q + 1 < KSC) {
+            d0f = stage[cur][TC::kDist + (q + 1) * 64 + lane];
+            d1f = stage[cur][TC::kDist + (KSC + q + 1) * 64 + lane];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int ab = 0; ab < NA; ++ab) {
+            if (!live[ab]) continue;
+            q0a[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0f, CA[ab][q], q0a[ab], 0, 0, 0);
+            q1a[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1f, CA[ab][q], q1a[ab], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          if (q + 1 < KSC) {
+            c0f = d0f;
+            c1f = d1f;
+          }
         }
       }
       bf16x8 H[NA], L[NA];
@@ -152,13 +196,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
       for (int ab = 0; ab < NA; ++ab) {
         const int64_t ar = (ablk0 + ab) * 16;
         if (!live[ab]) continue;
-        f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < KSC; ++q) {  // C fragments re-read per block (register budget)
-          q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[ab][q], q0, 0, 0, 0);
-          q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + (KSC + q) * 64 + lane], CA[ab][q], q1,
-                                                       0, 0, 0);
-        }
+        f32x4 q0 = q0a[ab], q1 = q1a[ab];
         if (b0 < ar + 16) {  // straddles the block: keep b > a only
           const int64_t am = ar + c16;
 #pragma unroll
@@ -189,16 +227,27 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
         }
         split_bf16x8(pv, H[ab], L[ab]);
       }
+      bf16x8 Gh = stage[cur][TC::kDist + TC::kC + lane];
+      bf16x8 Gl = stage[cur][TC::kDist + TC::kC + 64 + lane];
 #pragma unroll
       for (int nb = 0; nb < NG; ++nb) {
-        const bf16x8 Gh = stage[cur][TC::kDist + TC::kC + (2 * nb) * 64 + lane];
-        const bf16x8 Gl = stage[cur][TC::kDist + TC::kC + (2 * nb + 1) * 64 + lane];
+        bf16x8 Nh, Nl;
+        if (nb + 1 < NG) {
+          Nh = stage[cur][TC::kDist + TC::kC + (2 * nb + 2) * 64 + lane];
+          Nl = stage[cur][TC::kDist + TC::kC + (2 * nb + 3) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ab = 0; ab < NA; ++ab) {
           if (!live[ab]) continue;
           acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gh, acc[ab][nb], 0, 0, 0);
           acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gl, acc[ab][nb], 0, 0, 0);
           acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L[ab], Gh, acc[ab][nb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (nb + 1 < NG) {
+          Gh = Nh;
+          Gl = Nl;
         }
       }
     }
