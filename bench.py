@@ -286,7 +286,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3 products (FP32 accumulate) / f64 solver",
+        "dtype": "fp16x3 distance + bf16x3 tile.V products (FP32 accumulate) / f64 solver",
         "data": "synthetic",
         "config": {"workload": "BBMM mll+gradient step, N=1,048,576 as two models (917,504 + 131,072 rows), "
                                "d=48, Matern-5/2 ARD, sigma^2=1e-3, [y | 15 probes], rank-100 pivoted Cholesky, "
