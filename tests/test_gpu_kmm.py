@@ -296,3 +296,9 @@ def test_mixed_form_out_of_range_coordinates_give_nan():
     assert np.all(np.isnan(got))
     ref = ok.khat_matmul(X, th, V.T).T
     assert col_rel_err(_run(th, X, V, "fp32"), ref) <= TOL["fp32"]
+    # a solve on such data stops with a non-finite error instead of running to max_iter
+    from paper_2109_09817_amd import _lib, gp
+    k = gp.Kernel(th.ell, th.sf, th.noise)
+    with pytest.raises(_lib.GpError) as e:
+        gp.mbcg(k, dev(X), dev(V), 50, 1e-6, precision="bf16x3")
+    assert e.value.code == _lib.GP_ENONFINITE
