@@ -60,9 +60,18 @@ constexpr int kTriFlush = 32;  // chunks per FP32 accumulation window
 // The largest C K-step count with two blocks per (KS, NJ) instantiation is read
 // off the compiled register counts.
 constexpr int tri_max_ksc2(int ks, int nj) {
-  return ks <= 4 && nj == 1 ? 12 : (ks <= 4 && nj <= 2 ? 8 : (ks == 5 && nj == 3 ? 4 : (ks == 7 && nj == 4 ? 1 : 0)));
+  return ks <= 4 && nj == 1 ? 12 : (ks <= 5 && nj <= 3 ? 8 : (ks == 7 && nj == 4 ? 2 : 0));
 }
 constexpr int tri_na(int ks, int ksc, int nj) { return ksc <= tri_max_ksc2(ks, nj) ? 2 : 1; }
+// The C^s phase runs for both row blocks at once (each staged C fragment read
+// once, the next K step's fragments read during the current MFMAs) where the
+// extra accumulators still fit; otherwise it runs block by block.
+constexpr int tri_max_ksc_joint(int ks, int nj) {
+  return ks <= 4 && nj == 1 ? 12 : (ks <= 4 && nj <= 2 ? 8 : (ks == 5 && nj == 3 ? 4 : (ks == 7 && nj == 4 ? 1 : 0)));
+}
+constexpr bool tri_joint_c(int ks, int ksc, int nj) {
+  return tri_na(ks, ksc, nj) == 1 || ksc <= tri_max_ksc_joint(ks, nj);
+}
 // Rows of one row group (a workgroup's register-resident rows).
 constexpr int tri_rows(int ks, int ksc, int nj) { return 16 * kTriWaves * tri_na(ks, ksc, nj); }
 

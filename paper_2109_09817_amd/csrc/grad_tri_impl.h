@@ -159,15 +159,17 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
           b1f = n1f;
         }
       }
-      // C^s tiles of the NA blocks, one staged K step at a time, the next
-      // step's fragments read while these MFMAs run
+      // C^s tiles: both blocks one staged K step at a time, the next step's
+      // fragments read while these MFMAs run, where the registers allow;
+      // otherwise block by block (the fragments re-read per block)
+      constexpr bool kJoint = tri_joint_c(KS, KSC, NJ);
       f32x4 q0a[NA], q1a[NA];
+      if constexpr (kJoint) {
 #pragma unroll
-      for (int ab = 0; ab < NA; ++ab) {
-        q0a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
-        q1a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-      {
+        for (int ab = 0; ab < NA; ++ab) {
+          q0a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+          q1a[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
         bf16x8 c0f = stage[cur][TC::kDist + lane];
         bf16x8 c1f = stage[cur][TC::kDist + KSC * 64 + lane];
 #pragma unroll
@@ -196,7 +198,18 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
       for (int ab = 0; ab < NA; ++ab) {
         const int64_t ar = (ablk0 + ab) * 16;
         if (!live[ab]) continue;
-        f32x4 q0 = q0a[ab], q1 = q1a[ab];
+        f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (kJoint) {
+          q0 = q0a[ab];
+          q1 = q1a[ab];
+        } else {
+#pragma unroll
+          for (int q = 0; q < KSC; ++q) {
+            q0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + q * 64 + lane], CA[ab][q], q0, 0, 0, 0);
+            q1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(stage[cur][TC::kDist + (KSC + q) * 64 + lane], CA[ab][q],
+                                                         q1, 0, 0, 0);
+          }
+        }
         if (b0 < ar + 16) {  // straddles the block: keep b > a only
           const int64_t am = ar + c16;
 #pragma unroll
