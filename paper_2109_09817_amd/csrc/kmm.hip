@@ -1146,38 +1146,42 @@ __global__ __launch_bounds__(256) void sweep_fp64_kernel(const double* __restric
   f64x4 acc[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t b0 = 0; b0 < n; b0 += kF64Chunk) {
-    {
-      // every staging load of a thread in flight before its first LDS write
-      constexpr int kBPer = kF64Chunk * DP / 256, kVPer = kF64Chunk * kF64Cols / 256;
-      double bv[kBPer], vv[kVPer];
+  // staging: the next chunk's points, V and norms are loaded into registers
+  // while the current chunk is computed from LDS
+  constexpr int kBPer = kF64Chunk * DP / 256, kVPer = kF64Chunk * kF64Cols / 256;
+  double bv[kBPer], vv[kVPer], nv;
+  auto load = [&](int64_t c0b) {
 #pragma unroll
-      for (int it = 0; it < kBPer; ++it) {
-        const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
-        const int64_t b = b0 + j;
-        bv[it] = (b < n && f < d) ? Xb[b * d + f] : 0.0;
-      }
-#pragma unroll
-      for (int it = 0; it < kVPer; ++it) {
-        const int e = tid + 256 * it, c = e / kF64Chunk, j = e - c * kF64Chunk;
-        const int64_t b = b0 + j;
-        vv[it] = (b < n && c < tc) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
-      }
-      const double nv = (tid < kF64Chunk && b0 + tid < n) ? nb[b0 + tid] : 0.0;
-      __syncthreads();  // the previous chunk's readers are done
-#pragma unroll
-      for (int it = 0; it < kBPer; ++it) {
-        const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
-        Bs[j * kBLd + f] = bv[it] * bs[it];
-      }
-#pragma unroll
-      for (int it = 0; it < kVPer; ++it) {
-        const int e = tid + 256 * it, c = e / kF64Chunk;
-        Vs[c * kVLd + e - c * kF64Chunk] = vv[it];
-      }
-      if (tid < kF64Chunk) Ns[tid] = nv;
+    for (int it = 0; it < kBPer; ++it) {
+      const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
+      const int64_t b = c0b + j;
+      bv[it] = (b < n && f < d) ? Xb[b * d + f] : 0.0;
     }
+#pragma unroll
+    for (int it = 0; it < kVPer; ++it) {
+      const int e = tid + 256 * it, c = e / kF64Chunk, j = e - c * kF64Chunk;
+      const int64_t b = c0b + j;
+      vv[it] = (b < n && c < tc) ? V[(int64_t)(c0 + c) * ldv + b] : 0.0;
+    }
+    nv = (tid < kF64Chunk && c0b + tid < n) ? nb[c0b + tid] : 0.0;
+  };
+  load(0);
+  for (int64_t b0 = 0; b0 < n; b0 += kF64Chunk) {
+    __syncthreads();  // the previous chunk's readers are done
+#pragma unroll
+    for (int it = 0; it < kBPer; ++it) {
+      const int e = tid + 256 * it, j = e / DP, f = e - j * DP;
+      Bs[j * kBLd + f] = bv[it] * bs[it];
+    }
+#pragma unroll
+    for (int it = 0; it < kVPer; ++it) {
+      const int e = tid + 256 * it, c = e / kF64Chunk;
+      Vs[c * kVLd + e - c * kF64Chunk] = vv[it];
+    }
+    if (tid < kF64Chunk) Ns[tid] = nv;
     __syncthreads();
+    if (b0 + kF64Chunk < n) load(b0 + kF64Chunk);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int pb = 0; pb < 2; ++pb) {
       // x_b . x_a: D(point 16 pb + lk + 4 i, row arow)
