@@ -61,10 +61,11 @@ extern "C" {
 #define GP_PREC_FP32 0   /* FP32 matrix-core operands and accumulation */
 /* Mixed: every operand split hi + lo, three products hi.hi + hi.lo + lo.hi, FP32
  * accumulation.  The distance uses FP16 halves of the scaled coordinates centred on the
- * first training point (22 significant bits), the kernel values and vectors BF16 halves.
- * FP16 bounds the scaled coordinates: |x_j - x_0j| / l_j up to about 10^4 (Matern-5/2;
- * about 3.8 10^4 for RBF).  A point beyond makes every product involving it NaN (gp_mbcg
- * then fails with GP_ENONFINITE); GP_PREC_FP32 has no such bound. */
+ * training points' column means m (22 significant bits), the kernel values and vectors
+ * BF16 halves.  FP16 bounds the scaled coordinates: |x_j - m_j| / l_j up to about 10^4
+ * (Matern-5/2; about 3.8 10^4 for RBF), for training and query rows alike.  A point beyond
+ * makes every product involving it NaN (gp_mbcg then fails with GP_ENONFINITE);
+ * GP_PREC_FP32 has no such bound. */
 #define GP_PREC_BF16X3 1
 #define GP_PREC_FP64 2   /* FP64 throughout (low-noise regime); gp_kmm, gp_mbcg and gp_bcg only, d <= 64 */
 

@@ -27,27 +27,6 @@ namespace gpk {
 
 constexpr int kGradFlush = 32;
 
-// Column means of the row-major n x d matrix X (two passes, fixed order).
-__global__ void colmean_partial_kernel(const double* __restrict__ X, int64_t n, int d, int64_t rows_per_blk,
-                                       double* __restrict__ part) {
-  const int j = threadIdx.x;
-  if (j >= d) return;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
-  double s = 0.0;
-  for (int64_t i = r0; i < r1; ++i) s += X[i * d + j];
-  part[(int64_t)blockIdx.x * d + j] = s;
-}
-
-__global__ void colmean_final_kernel(const double* __restrict__ part, int64_t nblk, int d, int64_t n,
-                                     double* __restrict__ mu) {
-  const int j = threadIdx.x;
-  if (j >= d) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += part[b * d + j];
-  mu[j] = s / (double)n;
-}
-
 // float4 fragments of t columns of a column-major block, optionally weighted:
 // (blk, q, lane) -> w_c M[c*ld + p] for c = 16 q + 4 s + lane/16, p = 16 blk + lane%16.
 __global__ void prep_colfrag_kernel(const double* __restrict__ M, int64_t ld, int64_t n, int t,
@@ -448,7 +427,8 @@ size_t grad_ws_bytes(int precision, int d, int64_t n, int t) {
   b += align256((size_t)(d + 1) * 8);                            // reduced
   b += align256((size_t)t * 8) + 2 * align256((size_t)d * 8);    // weights, mean, 1/l
   b += align256((size_t)std::max<int64_t>(g.nunits, 1) * sizeof(int2));  // unit table
-  b += align256((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t) * 8);  // reductions
+  b += align256(std::max((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t), colmean_scratch_doubles(n, d)) *
+                8);  // reductions, column means
   b += align256((size_t)t * 8);                                  // U_c . W_c
   return b + 4096;
 }
@@ -504,7 +484,8 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   double* mu = cv.take<double>(d);
   double* inv_dev = cv.take<double>(d);
   int2* unit_dev = cv.take<int2>((size_t)std::max<int64_t>(g.nunits, 1));
-  double* rpart = cv.take<double>((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t));
+  double* rpart = cv.take<double>(std::max((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t),
+                                           colmean_scratch_doubles(n, d)));
   double* uw = cv.take<double>(t);
   if (!uw) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace layout failed");
   std::vector<double> invh(d);
@@ -512,17 +493,13 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
   std::vector<int2> units;
   GPK_HIP(hipMemcpyAsync(wdev, colw, sizeof(double) * t, hipMemcpyHostToDevice, st));
   GPK_HIP(hipMemcpyAsync(inv_dev, invh.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
-  {
-    const RowSplit rs = row_split(n, kDotBlocks);
-    colmean_partial_kernel<<<(unsigned)rs.nblk, 128, 0, st>>>(X, n, d, rs.rows_per_blk, rpart);
-    colmean_final_kernel<<<1, 128, 0, st>>>(rpart, rs.nblk, d, n, mu);
-  }
+  GPK_HIP(column_means(X, n, d, rpart, mu, st));
   const unsigned thr = 256;
   char* dxr = (char*)ws;  // BF16X3 form: [b-side | a-side | norms] at the front of ws
   char* dxc = dxr + align256((size_t)g.mpad * g.ks * 64);
   double* dxn = (double*)(dxc + align256((size_t)g.mpad * g.ks * 64));
   if (g.mixed)
-    GPK_HIP(prep_dist(kern, X, n, g.mpad, g.ks, dxr, dxc, dxn, st));
+    GPK_HIP(prep_dist(kern, X, n, g.mpad, g.ks, mu, dxr, dxc, dxn, st));
   else
     GPK_HIP(kmm_prepare(plan, kern, X, nullptr, st));
   bool ok = false;

@@ -15,7 +15,7 @@
 // first chunk; pairs with b <= a inside a chunk that straddles a block are
 // masked.  Per (16 rows) x (32 points) tile, on the matrix cores:
 //   S    = |x~_a - x~_b|^2          (distance, K = 3d + 6: FP16 hi/lo coordinates
-//                                    centred on the first point, the products
+//                                    centred on the column means, the products
 //                                    hi.hi + hi.lo + lo.hi and the norm digits)
 //   C^s  = [W_b | U_b] . [w U_a | w W_a]^T   (K = 2t, split three ways)
 //   P    = psi(S) C^s, its row sums, and sum k(S) C^s   (registers, FP32)

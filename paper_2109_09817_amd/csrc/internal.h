@@ -46,7 +46,8 @@ struct KmmPlan {
   float* nrm_b = nullptr;   // FP32 form: norms of the b stream
   float* nrm_a = nullptr;   // FP32 form: norms of the output rows
   double* nrm64 = nullptr;  // FP64 norms scratch (n or m entries)
-  double* ctr = nullptr;    // mixed form: the centre of the coordinates (the b stream's first point, d values)
+  double* ctr = nullptr;    // mixed form: the centre of the coordinates (the b stream's column means, d values)
+  double* cpart = nullptr;  // scratch of the column means (colmean_scratch_doubles(n, d))
   void* vf = nullptr;
   double* part = nullptr;
   int64_t part_splits = 0;  // splits the partial buffer can hold
@@ -80,11 +81,16 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
 hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
                      hipStream_t st, bool row_independent);
 // The mixed form's FP16 distance operands of a square product (prep_frag_f16x3_kernel)
-// at ks K steps of 32 (ks * 32 >= 3d + 6): the b-side (xr) and a-side (xc)
-// fragments of rows_pad points (a multiple of 64; points >= n are zero), with
-// nrm64 (rows_pad doubles) as scratch for the squared norms.
-hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
-                     void* xc, double* nrm64, hipStream_t st);
+// at ks K steps of 32 (ks * 32 >= 3d + 6), centred on ctr (d device values, the
+// column means of X): the b-side (xr) and a-side (xc) fragments of rows_pad points
+// (a multiple of 64; points >= n are zero), with nrm64 (rows_pad doubles) as
+// scratch for the squared norms.
+hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, const double* ctr,
+                     void* xr, void* xc, double* nrm64, hipStream_t st);
+// Column means of the row-major n x d matrix X into mu (d doubles), deterministic;
+// part: colmean_scratch_doubles(n, d) doubles of scratch.
+size_t colmean_scratch_doubles(int64_t n, int d);
+hipError_t column_means(const double* X, int64_t n, int d, double* part, double* mu, hipStream_t st);
 // Bytes of the V fragments for t columns.
 size_t kmm_vfrag_bytes(int64_t n, int t);
 // A cross-product plan split in two: the training-side operands (b stream and V

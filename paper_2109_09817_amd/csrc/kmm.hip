@@ -25,7 +25,7 @@
 //
 // Two arithmetic forms share this structure:
 //   BF16X3: the distance from FP16 hi/lo coordinates (centred on the b
-//           stream's first point) with the three products hi.hi + hi.lo + lo.hi
+//           stream's column means) with the three products hi.hi + hi.lo + lo.hi
 //           on v_mfma_f32_16x16x32_f16; M and V split x = hi + lo in BF16 (round
 //           to nearest even, BF16 for its exponent range: kernel values and
 //           vectors span many decades), the same three products on
@@ -88,8 +88,9 @@ __device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(f
 // x' ~ h + l, h = RNE16(x'), l = RNE16(x' - h) (22 significant bits), and the
 // three products h.h + h.l + l.h; n = sum (h + l)^2, so that the dropped l.l
 // leaves an error of 2 l_a . l_b (about 2^-22 |x'|^2, of either sign) instead of a
-// bias.  The centre c is the first point of the b stream (the training points),
-// so the coordinates stay small whatever the data's offset.  FP16 holds
+// bias.  The centre c is the column mean of the b stream (the training points),
+// so the coordinates, and with them the cancellation in n_a + n_b - 2 x'_a . x'_b,
+// stay as small as the data's spread allows whatever its offset.  FP16 holds
 // |h| <= 32752 (-2h must stay finite): a point with a scaled coordinate beyond
 // that, about 10^4 lengthscales from the centre, gets a NaN norm, and every
 // product involving it is NaN (never silently wrong).  The norms enter the K
@@ -102,14 +103,53 @@ constexpr double kMaxNorm = 65504.0 * 32768.0;              // largest n the top
 
 __device__ __forceinline__ double f16_round(double x) { return (double)(_Float16)(float)x; }
 
+// Column means of the row-major n x d matrix X (the centre of the mixed form), in
+// two fixed-order passes: sums over blocks of consecutive rows, then over the
+// blocks, so that repeated runs give the same bits.
+constexpr int64_t kMeanBlocks = 1024;
+
+static int64_t colmean_blocks(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(kMeanBlocks, (n + 255) / 256));
+}
+
+size_t colmean_scratch_doubles(int64_t n, int d) { return (size_t)colmean_blocks(n) * (size_t)d; }
+
+__global__ void colmean_partial_kernel(const double* __restrict__ X, int64_t n, int d, int64_t rows_per_blk,
+                                       double* __restrict__ part) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
+  double s = 0.0;
+#pragma unroll 4
+  for (int64_t i = r0; i < r1; ++i) s += X[i * d + j];
+  part[(int64_t)blockIdx.x * d + j] = s;
+}
+
+__global__ void colmean_final_kernel(const double* __restrict__ part, int64_t nblk, int d, int64_t n,
+                                     double* __restrict__ mu) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) s += part[b * d + j];
+  mu[j] = s / (double)n;
+}
+
+hipError_t column_means(const double* X, int64_t n, int d, double* part, double* mu, hipStream_t st) {
+  if (!X || !part || !mu || n < 1 || d < 1 || d > GP_MAX_D) return hipErrorInvalidValue;
+  const int64_t nblk = colmean_blocks(n);
+  const int64_t rpb = (n + nblk - 1) / nblk;
+  colmean_partial_kernel<<<(unsigned)nblk, 128, 0, st>>>(X, n, d, rpb, part);
+  colmean_final_kernel<<<1, 128, 0, st>>>(part, nblk, d, n, mu);
+  return hipGetLastError();
+}
+
 // Squared norm of each prepared point (FP64).  mode 1 (mixed form): the centred
 // FP16 split above, n = sum (h + l)^2, NaN out of range.  mode 0 (FP32 form):
-// n = sum f^2 with f = fl32(x s), no centring.  ctr: the centre (d values, mode 1);
-// ctr_save (optional): a copy of the centre written by block 0, for the query
-// rows prepared later against the same b stream.
+// n = sum f^2 with f = fl32(x s), no centring.  ctr: the centre (d values, mode 1).
 __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict__ X, int64_t n, int64_t npad,
                                                         int d, Scale sc, int mixed, const double* __restrict__ ctr,
-                                                        double* __restrict__ ctr_save, double* __restrict__ nrm) {
+                                                        double* __restrict__ nrm) {
   // Each wave owns 64 consecutive points.  Per slice of 16 features the wave
   // loads the 64 x 16 block of X (each load instruction covers four rows'
   // 128-byte runs), turns every element into its norm term and parks the terms
@@ -121,8 +161,6 @@ __global__ __launch_bounds__(256) void prep_norm_kernel(const double* __restrict
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
   const int fl = lane & 15;
-  if (ctr_save && blockIdx.x == 0)
-    for (int j = threadIdx.x; j < d; j += blockDim.x) ctr_save[j] = ctr[j];
   double s = 0.0;
   if (n > 0) {  // the same for the whole block
     for (int j0 = 0; j0 < d; j0 += kF) {
@@ -964,6 +1002,7 @@ size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, i
   b += align256((size_t)mpad * 4);                 // nrm_a
   b += align256((size_t)bpad * 8);                 // nrm64
   b += align256((size_t)d * 8);                    // ctr
+  b += align256(colmean_scratch_doubles(n, d) * 8);  // column-mean partials
   b += align256((size_t)npad * ntb * 64 + 64);     // vf
   b += align256(part_bytes_max(npad, mpad, ntb0, !square, ks, precision == GP_PREC_BF16X3));  // partials
   return b;
@@ -1002,21 +1041,22 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
   p.nrm_a = (float*)c;  c += align256((size_t)p.mpad * 4);
   p.nrm64 = (double*)c; c += align256((size_t)bpad * 8);
   p.ctr = (double*)c;   c += align256((size_t)p.d * 8);
+  p.cpart = (double*)c; c += align256(colmean_scratch_doubles(n, p.d) * 8);
   const int ntb_alloc = (p.ntb + nt_launch(p.ntb) - 1) / nt_launch(p.ntb) * nt_launch(p.ntb);
   p.vf = c;  c += align256((size_t)p.npad * ntb_alloc * 64 + 64);
   p.part = (double*)c;
   return true;
 }
 
-// Model buffer: [b-stream fragments | b norms (FP32) | V fragments | centre (d) | FP64 norm scratch of the
-// prepare step].
+// Model buffer: [b-stream fragments | b norms (FP32) | V fragments | centre (d) | column-mean and FP64 norm
+// scratch of the prepare step].
 size_t kmm_model_bytes(int precision, int d, int64_t n, int tmax) {
   if (precision == GP_PREC_FP64) return 0;  // prediction models use the matrix-core forms
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
   const int64_t npad = round_up(n, 32);
   return align256((size_t)npad * ks * 64) + align256((size_t)npad * 4) + kmm_vfrag_bytes(n, tmax) +
-         align256((size_t)d * 8) + align256((size_t)npad * 8);
+         align256((size_t)d * 8) + align256(colmean_scratch_doubles(n, d) * 8) + align256((size_t)npad * 8);
 }
 
 // Query workspace: [row fragments | row norms (FP32) | FP64 norm scratch | partials].
@@ -1054,6 +1094,7 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
   p.nrm_b = (float*)c;  c += align256((size_t)p.npad * 4);
   p.vf = c;  c += kmm_vfrag_bytes(n, tmax);
   p.ctr = (double*)c;  c += align256((size_t)p.d * 8);
+  p.cpart = (double*)c;  c += align256(colmean_scratch_doubles(n, p.d) * 8);
   if (m > 0) {
     char* w = (char*)ws;
     p.xc = w;  w += align256((size_t)p.mpad * p.ks * 64);
@@ -1281,22 +1322,27 @@ static Scale make_scale(const gp_kernel* kern) {
   return s;
 }
 
-// ctr: the centre of the mixed form's coordinates (the b stream's first point);
-// ctr_save (optional): where to keep a copy of it for later query rows.
+// set_centre: P is the b stream (the training points), whose column means become
+// the centre of the mixed form's coordinates (p.ctr); otherwise P is query rows,
+// prepared against the centre already in p.ctr.
 static hipError_t prep_points(const KmmPlan& p, const Scale& sc, const double* P, int64_t rows,
-                              int64_t rows_pad, void* xr, void* xc, float* nr, float* nc, const double* ctr,
-                              double* ctr_save, hipStream_t st) {
+                              int64_t rows_pad, void* xr, void* xc, float* nr, float* nc, bool set_centre,
+                              hipStream_t st) {
   if (!p.nrm64 || !P || (!xr && !xc)) return hipErrorInvalidValue;
   const int mixed = p.precision == GP_PREC_BF16X3;
-  if (mixed && !ctr) return hipErrorInvalidValue;
+  if (mixed && (!p.ctr || (set_centre && !p.cpart))) return hipErrorInvalidValue;
+  if (mixed && set_centre) {
+    const hipError_t e = column_means(P, rows, p.d, p.cpart, p.ctr, st);
+    if (e != hipSuccess) return e;
+  }
   const int thr = 256;
-  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(
-      P, rows, rows_pad, p.d, sc, mixed, mixed ? ctr : nullptr, mixed ? ctr_save : nullptr, p.nrm64);
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(P, rows, rows_pad, p.d, sc, mixed,
+                                                                           mixed ? p.ctr : nullptr, p.nrm64);
   const int64_t nblk = rows_pad / 16;
   const int64_t total = nblk * p.ks * 64;
   if (mixed) {
     prep_frag_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
-        P, p.nrm64, ctr, rows, nblk, p.d, p.ks, sc, (bf16x8*)xr, (bf16x8*)xc);
+        P, p.nrm64, p.ctr, rows, nblk, p.d, p.ks, sc, (bf16x8*)xr, (bf16x8*)xc);
   } else {
     prep_frag_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
         P, p.nrm64, rows, nblk, p.d, p.ks, sc, (f32x4*)xr, (f32x4*)xc, nr, nc);
@@ -1322,7 +1368,7 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
   if (p.square) {
     // one pass gives both sides; rows up to max(npad, mpad) so xc covers mpad
     const int64_t rows_pad = std::max(p.npad, p.mpad);
-    return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, X, nullptr, st);
+    return prep_points(p, sc, X, p.n, rows_pad, p.xr, p.xc, p.nrm_b, p.nrm_a, true, st);
   }
   hipError_t e = kmm_prepare_rows(p, kern, X, st);
   if (e != hipSuccess) return e;
@@ -1331,25 +1377,26 @@ hipError_t kmm_prepare(KmmPlan& p, const gp_kernel* kern, const double* X, const
 
 hipError_t kmm_prepare_rows(KmmPlan& p, const gp_kernel* kern, const double* X, hipStream_t st) {
   if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
-  return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, X, p.ctr, st);
+  return prep_points(p, make_scale(kern), X, p.n, p.npad, p.xr, nullptr, p.nrm_b, nullptr, true, st);
 }
 
 hipError_t kmm_prepare_cols(KmmPlan& p, const gp_kernel* kern, const double* Z, hipStream_t st) {
   if (p.precision == GP_PREC_FP64) return hipErrorInvalidValue;
-  return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, p.ctr, nullptr, st);
+  return prep_points(p, make_scale(kern), Z, p.m, p.mpad, nullptr, p.xc, nullptr, p.nrm_a, false, st);
 }
 
-hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, void* xr,
-                     void* xc, double* nrm64, hipStream_t st) {
-  if (!X || !nrm64 || (!xr && !xc) || ks * 32 < 3 * kern->d + 6 || rows_pad % 64 != 0) return hipErrorInvalidValue;
+hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t rows_pad, int ks, const double* ctr,
+                     void* xr, void* xc, double* nrm64, hipStream_t st) {
+  if (!X || !ctr || !nrm64 || (!xr && !xc) || ks * 32 < 3 * kern->d + 6 || rows_pad % 64 != 0)
+    return hipErrorInvalidValue;
   const Scale sc = make_scale(kern);
   const int thr = 256;
-  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(X, n, rows_pad, kern->d, sc, 1, X,
-                                                                           nullptr, nrm64);
+  prep_norm_kernel<<<(unsigned)((rows_pad + thr - 1) / thr), thr, 0, st>>>(X, n, rows_pad, kern->d, sc, 1, ctr,
+                                                                           nrm64);
   const int64_t nblk = rows_pad / 16;
   const int64_t total = nblk * ks * 64;
-  prep_frag_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(X, nrm64, X, n, nblk, kern->d, ks, sc,
-                                                                             (bf16x8*)xr, (bf16x8*)xc);
+  prep_frag_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(X, nrm64, ctr, n, nblk, kern->d, ks,
+                                                                             sc, (bf16x8*)xr, (bf16x8*)xc);
   return hipGetLastError();
 }
 

@@ -266,7 +266,7 @@ def test_mid_size_square_products_match_oracle(n, d, t, kind):
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
 def test_products_do_not_depend_on_an_offset_of_the_data(prec):
     """The kernel depends on differences only.  The mixed form centres its FP16 coordinates on the
-    first training point, so shifting every point (training and query) by 10^4 lengthscales leaves
+    training points' column means, so shifting every point (training and query) by 10^4 lengthscales leaves
     its results at the unshifted accuracy; the FP32 form's norms are not centred and are checked
     only at a small offset."""
     n, d, t, m = 3000, 48, 9, 155
@@ -284,9 +284,31 @@ def test_products_do_not_depend_on_an_offset_of_the_data(prec):
     assert err_off <= TOL_OFF[prec] and errc <= TOL_OFF[prec]
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_products_with_an_outlying_first_point(prec):
+    """The first training point moved 100 lengthscales away from the rest: the mixed form's centre is
+    the column mean, not a data point, so the other points' coordinates stay small and their distances
+    keep their accuracy."""
+    n, d, t, m = 3000, 48, 9, 155
+    X, th, V = _case(n, d, t, True, seed=29)
+    X = X.copy()
+    X[0] += 100.0 * th.ell
+    Z = synth.query_molecule("c2", m, seed=6)[:, :d]
+    ref = ok.khat_matmul(X, th, V.T).T
+    refc = ok.cross_matmul(Z, X, th, V.T).T
+    got = _run(th, X, V, prec)
+    gotc = _run(th, X, V, prec, Z=Z)
+    diag = (th.sf + th.noise) * V
+    err_off = col_rel_err(got - diag, ref - diag)
+    errc = float(np.linalg.norm(gotc - refc) / np.linalg.norm(refc))
+    print(f"outlying first point {prec}: square off-diagonal err {err_off:.3e}, cross err {errc:.3e}",
+          file=sys.stderr, flush=True)
+    assert err_off <= TOL_OFF[prec] and errc <= TOL_OFF[prec]
+
+
 def test_mixed_form_out_of_range_coordinates_give_nan():
     """A training point whose scaled coordinate lies beyond the FP16 range of the mixed form's distance
-    (about 10^4 lengthscales from the first point) makes the product NaN rather than silently wrong;
+    (about 10^4 lengthscales from the training points' column means) makes the product NaN rather than silently wrong;
     the FP32 form still computes it."""
     n, d, t = 700, 16, 3
     X, th, V = _case(n, d, t, True, seed=23)

@@ -243,7 +243,11 @@ def test_gradient_forms_at_workload_vectors(prec, cond):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("kind", [ok.MATERN52, ok.RBF])
-@pytest.mark.parametrize("n,d,t", [(1500, 48, 9), (700, 7, 3), (2049, 32, 33), (1100, 64, 64), (5000, 48, 16)])
+# every instantiated shape class of the triangle sweep: (K steps, form blocks) = (2, 1), (4, 2), (5, 3),
+# (7, 4); the C^s phase joint for both row blocks (t = 9 at d = 48), block by block with two row blocks
+# (t = 9 at d = 64) and with one (t = 64 at d = 64)
+@pytest.mark.parametrize("n,d,t", [(1500, 48, 9), (700, 7, 3), (2049, 32, 33), (1100, 64, 64), (5000, 48, 16),
+                                   (900, 64, 9)])
 def test_kmm_grad_matches_oracle(n, d, t, kind, prec):
     from paper_2109_09817_amd import gp
     X, y, th0 = _problem(n, d, True)
