@@ -60,8 +60,9 @@ def _definition(text, name):
 
 
 # The sweep kernel and everything it executes: its source text decides whether recorded counters apply.
-SWEEP_SOURCES = [("paper_2109_09817_amd/csrc/kmm.hip", ["profile", "NAOf", "ChunkUnits", "sweep_bf16x3_kernel"]),
-                 ("paper_2109_09817_amd/csrc/mfma_bf16.h", ["split_bf16x8", "mfma_dist", "vperm"])]
+SWEEP_SOURCES = [("paper_2109_09817_amd/csrc/kmm.hip", ["profile_scaled", "NAOf", "ChunkUnits", "sweep_bf16x3_kernel"]),
+                 ("paper_2109_09817_amd/csrc/mfma_bf16.h", ["f16_residual_pair", "split_f16x8", "mfma_val", "mfma_dist",
+                                                            "vperm"])]
 
 
 def sweep_source_digest():
@@ -296,7 +297,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp16x3 distance + bf16x3 tile.V products (FP32 accumulate) / f64 solver",
+        "dtype": "fp16x3 distance and tile.V products (FP32 accumulate) / f64 solver",
         "data": "synthetic",
         "config": {"workload": "BBMM mll+gradient step, N=1,048,576 as two models (917,504 + 131,072 rows), "
                                "d=48, Matern-5/2 ARD, sigma^2=1e-3, [y | 15 probes], rank-100 pivoted Cholesky, "

@@ -59,10 +59,13 @@ extern "C" {
 
 /* ---- arithmetic of the kernel-matrix products ---- */
 #define GP_PREC_FP32 0   /* FP32 matrix-core operands and accumulation */
-/* Mixed: every operand split hi + lo, three products hi.hi + hi.lo + lo.hi, FP32
- * accumulation.  The distance uses FP16 halves of the scaled coordinates centred on the
- * training points' column means m (22 significant bits), the kernel values and vectors
- * BF16 halves.  FP16 bounds the scaled coordinates: |x_j - m_j| / l_j up to about 10^4
+/* Mixed: every operand split hi + lo in FP16 (22 significant bits), three products
+ * hi.hi + hi.lo + lo.hi on the FP16 matrix cores, FP32 accumulation.  The distance uses
+ * the scaled coordinates centred on the training points' column means m; the kernel
+ * values enter as 2^15 m(r) and each column of V scaled by the power of two that puts
+ * its largest entry in [2^14, 2^15), scalings undone exactly in FP64 (in gp_kmm_grad the
+ * kernel-weighted values and the columns [x~ | x~^2] keep BF16 halves).  FP16 bounds the
+ * scaled coordinates: |x_j - m_j| / l_j up to about 10^4
  * (Matern-5/2; about 3.8 10^4 for RBF), for training and query rows alike.  A point beyond
  * makes every product involving it NaN (gp_mbcg then fails with GP_ENONFINITE);
  * GP_PREC_FP32 has no such bound. */

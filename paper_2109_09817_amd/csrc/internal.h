@@ -49,6 +49,9 @@ struct KmmPlan {
   double* ctr = nullptr;    // mixed form: the centre of the coordinates (the b stream's column means, d values)
   double* cpart = nullptr;  // scratch of the column means (colmean_scratch_doubles(n, d))
   void* vf = nullptr;
+  double* vscale = nullptr;  // mixed form: per-column power-of-two scale of V's fragments (tpad values)
+  double* vinv = nullptr;    // mixed form: 2^-15 / vscale, applied to the partial sums (tpad values)
+  double* vpart = nullptr;   // mixed form: column-max partials (scratch of kmm_prepare_v)
   double* part = nullptr;
   int64_t part_splits = 0;  // splits the partial buffer can hold
   // FP64 form: the points themselves (caller memory), prescaled features and norms

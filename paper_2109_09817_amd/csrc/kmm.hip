@@ -24,12 +24,14 @@
 // in FP64 by the epilogue as (s_f + sigma^2) V.
 //
 // Two arithmetic forms share this structure:
-//   BF16X3: the distance from FP16 hi/lo coordinates (centred on the b
-//           stream's column means) with the three products hi.hi + hi.lo + lo.hi
-//           on v_mfma_f32_16x16x32_f16; M and V split x = hi + lo in BF16 (round
-//           to nearest even, BF16 for its exponent range: kernel values and
-//           vectors span many decades), the same three products on
-//           v_mfma_f32_16x16x32_bf16; FP32 accumulation.
+//   BF16X3 (the mixed form; the name is the ABI's): the distance from FP16
+//           hi/lo coordinates (centred on the b stream's column means) with the
+//           three products hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_f16; M
+//           and V split x = hi + lo in FP16 as well, after power-of-two scalings
+//           that keep them in FP16's normal range (2^15 M; each column of V so
+//           that its largest entry lies in [2^14, 2^15)), the same three
+//           products on the same instruction; FP32 accumulation, the scalings
+//           undone exactly in the FP64 epilogue.
 //   FP32:   v_mfma_f32_16x16x4_f32 for both products; the squared norms
 //           initialise the distance accumulator.
 // Row-independent BF16X3 cross products with many columns (prediction) use a
@@ -79,7 +81,18 @@ __device__ __forceinline__ float profile(float S) {
   }
 }
 
-__device__ __forceinline__ float bf16_round(double x) { return (float)(__bf16)(float)x; }
+// kMScale m(r) for the mixed form's FP16 value products: the Matern scale rides in
+// the polynomial's constants, the RBF one costs a multiply.
+template <int KIND>
+__device__ __forceinline__ float profile_scaled(float S) {
+  if constexpr (KIND == GP_MATERN52) {
+    const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(S));
+    const float e = __builtin_amdgcn_exp2f(-u);
+    return __builtin_fmaf(__builtin_fmaf(u, kMaternC2s, kMaternC1s), u, kMScale) * e;
+  } else {
+    return __builtin_amdgcn_exp2f(-__builtin_fabsf(S)) * kMScale;
+  }
+}
 
 // ---------------------------------------------------------------- preparation
 //
@@ -286,10 +299,58 @@ __global__ void prep_frag_fp32_kernel(const double* __restrict__ X, const double
   }
 }
 
-// BF16X3 V fragments: (chunk, cb, hl, lane) -> 8 BF16 of V[b = 32 chunk + vperm(g, j)]
-// [c = 16 cb + lane%16], hl = 0 hi, 1 lo.
-__global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ col0,
-                                     int64_t n, int t, int64_t nchunks, int ntb, bf16x8* __restrict__ vf) {
+// Column scales of the mixed form's V fragments.  vmax_partial_kernel: the
+// largest |V| of each column over kVParts row ranges (NaN entries are skipped
+// here and reach the products through the values themselves); vscale_kernel:
+// scale[c] = 2^e with e = 15 - E, max |V_c| = f 2^E (f in [1/2, 1)), so that the
+// scaled column's largest entry lies in [2^14, 2^15), and inv[c] = 2^(-e - 15),
+// the factor that takes a partial sum of (kMScale m)(scale V) back to m V.  A zero
+// or non-finite column keeps scale 1.
+constexpr int kVParts = 64;
+
+__global__ __launch_bounds__(256) void vmax_partial_kernel(const double* __restrict__ V, int64_t ldv,
+                                                           const double* __restrict__ col0, int64_t n,
+                                                           double* __restrict__ part) {
+  __shared__ double red[256];
+  const int c = blockIdx.y;
+  const int64_t per = (n + kVParts - 1) / kVParts;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  const double* src = col0 ? (c == 0 ? col0 : V + (int64_t)(c - 1) * ldv) : V + (int64_t)c * ldv;
+  double mx = 0.0;
+  for (int64_t b = r0 + threadIdx.x; b < r1; b += 256) mx = fmax(mx, fabs(src[b]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)c * kVParts + blockIdx.x] = red[0];
+}
+
+__global__ void vscale_kernel(const double* __restrict__ part, int t, double* __restrict__ scale,
+                              double* __restrict__ inv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t) return;
+  double mx = 0.0;
+  for (int q = 0; q < kVParts; ++q) mx = fmax(mx, part[(int64_t)c * kVParts + q]);
+  int e = 0;
+  if (mx > 0.0 && mx <= 1.7976931348623157e308) {
+    int E = 0;
+    (void)frexp(mx, &E);
+    e = 15 - E;
+    e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+  }
+  scale[c] = ldexp(1.0, e);
+  inv[c] = ldexp(1.0, -e - 15);
+}
+
+// Mixed-form V fragments: (chunk, cb, hl, lane) -> 8 FP16 of v' = scale[c] V[b][c],
+// b = 32 chunk + vperm(g, j), c = 16 cb + lane%16; hl = 0: hi = RNE16(v'),
+// hl = 1: lo = RNE16(v' - hi).  Columns c >= t are zero.
+__global__ void prep_v_f16x3_kernel(const double* __restrict__ V, int64_t ldv, const double* __restrict__ col0,
+                                    const double* __restrict__ scale, int64_t n, int t, int64_t nchunks, int ntb,
+                                    bf16x8* __restrict__ vf) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nchunks * ntb * 64) return;
   const int lane = (int)(idx & 63);
@@ -298,17 +359,18 @@ __global__ void prep_v_bf16x3_kernel(const double* __restrict__ V, int64_t ldv, 
   const int64_t ch = rest / ntb;
   const int c = 16 * cb + (lane & 15);
   const int g = lane >> 4;
-  bf16x8 hi, lo;
+  const double sc = c < t ? scale[c] : 0.0;
+  f16x8 hi, lo;
   for (int j = 0; j < 8; ++j) {
     const int64_t b = ch * 32 + vperm(g, j);
     double v = 0.0;
-    if (b < n && c < t) v = col0 ? (c == 0 ? col0[b] : V[(int64_t)(c - 1) * ldv + b]) : V[(int64_t)c * ldv + b];
-    const float h = bf16_round(v);
-    hi[j] = (__bf16)h;
-    lo[j] = (__bf16)(float)(v - (double)h);
+    if (b < n && c < t) v = sc * (col0 ? (c == 0 ? col0[b] : V[(int64_t)(c - 1) * ldv + b]) : V[(int64_t)c * ldv + b]);
+    const double h = f16_round(v);
+    hi[j] = (_Float16)(float)h;
+    lo[j] = (_Float16)(float)(v - h);
   }
-  vf[(rest * 2 + 0) * 64 + lane] = hi;
-  vf[(rest * 2 + 1) * 64 + lane] = lo;
+  vf[(rest * 2 + 0) * 64 + lane] = __builtin_bit_cast(bf16x8, hi);
+  vf[(rest * 2 + 1) * 64 + lane] = __builtin_bit_cast(bf16x8, lo);
 }
 
 // FP32 V fragments: (chunk, cb, tile, lane) -> float4 of V[b = 32 chunk + 16 tile + 4g + i]
@@ -457,8 +519,8 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
       f32x8 mv;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        mv[i] = profile<KIND, false>(s0[i]);
-        mv[4 + i] = profile<KIND, false>(s1[i]);
+        mv[i] = profile_scaled<KIND>(s0[i]);
+        mv[4 + i] = profile_scaled<KIND>(s1[i]);
       }
       if (a.square) {
         const int64_t arow = (ablk0 + ab) * 16;
@@ -470,17 +532,12 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
         }
       }
       bf16x8 H, L;
-      // the one-instruction residual is faster with four column blocks per
-      // tile and slower with one (measured on the same tiles)
-      if constexpr (NT >= 4)
-        split_bf16x8_dot2(mv, H, L);
-      else
-        split_bf16x8(mv, H, L);
+      split_f16x8(mv, H, L);
 #pragma unroll
       for (int cb = 0; cb < NT; ++cb) {
-        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VH[cb], acc[ab][cb], 0, 0, 0);
-        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H, VL[cb], acc[ab][cb], 0, 0, 0);
-        acc[ab][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L, VH[cb], acc[ab][cb], 0, 0, 0);
+        acc[ab][cb] = mfma_val(H, VH[cb], acc[ab][cb]);
+        acc[ab][cb] = mfma_val(H, VL[cb], acc[ab][cb]);
+        acc[ab][cb] = mfma_val(L, VH[cb], acc[ab][cb]);
       }
     }
     if (((ch - c_begin + 1) % kFlush) == 0 || !more) {
@@ -515,7 +572,7 @@ __global__ __launch_bounds__(256, 2) void sweep_bf16x3_kernel(SweepArgs a) {
 // batch) and many columns (1 + k_c).  The sweep above evaluates each kernel
 // entry once per 64-column group; here a workgroup owns 64 query rows and all
 // columns of one chunk split.  Per 32-point chunk, wave w evaluates the
-// distances and the profile of row block w (16 rows) into an LDS tile (BF16
+// distances and the profile of row block w (16 rows) into an LDS tile (FP16
 // hi / lo, two buffers so that one barrier per chunk suffices); then every
 // wave multiplies the four row blocks' tiles by its own column blocks (cb = w,
 // w + 4, ...).  Both operand streams run one chunk ahead in registers: the
@@ -657,11 +714,11 @@ __global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
       f32x8 mv;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        mv[i] = profile<KIND, false>(s0[i]);
-        mv[4 + i] = profile<KIND, false>(s1[i]);
+        mv[i] = profile_scaled<KIND>(s0[i]);
+        mv[4 + i] = profile_scaled<KIND>(s1[i]);
       }
       bf16x8 H, L;
-      split_bf16x8(mv, H, L);
+      split_f16x8(mv, H, L);
       tile[cur][wave][0][lane] = H;
       tile[cur][wave][1][lane] = L;
     }
@@ -675,9 +732,9 @@ __global__ __launch_bounds__(256, 2) void wide_cross_bf16x3_kernel(WideArgs a) {
 #pragma unroll
       for (int jb = 0; jb < kWideNB; ++jb) {
         if (wave + 4 * jb < a.ntb) {
-          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TH, Vc[jb][0], acc[rb][jb], 0, 0, 0);
-          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TH, Vc[jb][1], acc[rb][jb], 0, 0, 0);
-          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(TL, Vc[jb][0], acc[rb][jb], 0, 0, 0);
+          acc[rb][jb] = mfma_val(TH, Vc[jb][0], acc[rb][jb]);
+          acc[rb][jb] = mfma_val(TH, Vc[jb][1], acc[rb][jb]);
+          acc[rb][jb] = mfma_val(TL, Vc[jb][0], acc[rb][jb]);
         }
       }
     }
@@ -809,16 +866,18 @@ __global__ __launch_bounds__(256, 2) void sweep_fp32_kernel(SweepArgs a) {
     }
 }
 
-// out[c*ldo + r] = s_f * sum_split part + (square ? (s_f + sigma^2) V[c*ldv + r] : 0)
+// out[c*ldo + r] = s_f * inv[c] * sum_split part + (square ? (s_f + sigma^2) V[c*ldv + r] : 0)
+// (inv: the mixed form's column factors, a power of two; null for the FP32 form)
 __global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsplit, int tpad,
                                     int64_t mpad, int64_t m, int t, double sf, double diag,
-                                    const double* __restrict__ V, int64_t ldv,
+                                    const double* __restrict__ inv, const double* __restrict__ V, int64_t ldv,
                                     double* __restrict__ out, int64_t ldo) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * t) return;
   const int64_t c = idx / m, r = idx - c * m;
   double s = 0.0;
   for (int64_t sp = 0; sp < nsplit; ++sp) s += part[(sp * tpad + c) * mpad + r];
+  if (inv) s *= inv[c];
   double o = sf * s;
   if (V) o += diag * V[c * ldv + r];
   out[c * ldo + r] = o;
@@ -830,6 +889,7 @@ __global__ void kmm_epilogue_kernel(const double* __restrict__ part, int64_t nsp
 template <typename T>
 __global__ __launch_bounds__(256) void wide_epilogue_kernel(const T* __restrict__ part, int64_t nsplit, int tpad,
                                                             int64_t mpad, int64_t m, double sf,
+                                                            const double* __restrict__ inv,
                                                             double* __restrict__ out, int64_t ldo) {
   __shared__ double red[4][64];
   const int r = threadIdx.x & 63;
@@ -853,7 +913,7 @@ __global__ __launch_bounds__(256) void wide_epilogue_kernel(const T* __restrict_
   }
   red[k][r] = s;
   __syncthreads();
-  if (k == 0 && q < m) out[c * ldo + q] = sf * (((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]);
+  if (k == 0 && q < m) out[c * ldo + q] = sf * ((((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]) * inv[c]);
 }
 
 // ------------------------------------------------------------------ host side
@@ -984,6 +1044,27 @@ static size_t part_bytes_max(int64_t npad, int64_t mpad, int ntb, bool row_indep
   return best;
 }
 
+// V region: [fragments | scale (tpad) | inv (tpad) | column-max partials (kVParts tpad)].
+static size_t vfrag_core_bytes(int64_t n, int ntb_alloc) {
+  return align256((size_t)round_up(n, 32) * ntb_alloc * 64 + 64);
+}
+
+size_t kmm_vfrag_bytes(int64_t n, int t) {
+  const int ntb0 = (t + 15) / 16;
+  const int ntb = (ntb0 + nt_launch(ntb0) - 1) / nt_launch(ntb0) * nt_launch(ntb0);
+  return vfrag_core_bytes(n, ntb) + 2 * align256((size_t)ntb * 16 * 8) + align256((size_t)kVParts * ntb * 16 * 8);
+}
+
+static void carve_vfrag(KmmPlan& p, char* c) {
+  const int ntb_alloc = (p.ntb + nt_launch(p.ntb) - 1) / nt_launch(p.ntb) * nt_launch(p.ntb);
+  const int tpad = ntb_alloc * 16;
+  p.vf = c;
+  c += vfrag_core_bytes(p.n, ntb_alloc);
+  p.vscale = (double*)c;  c += align256((size_t)tpad * 8);
+  p.vinv = (double*)c;    c += align256((size_t)tpad * 8);
+  p.vpart = (double*)c;
+}
+
 size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, int tmax) {
   const int ks = kmm_ksteps(precision, d);
   if (ks < 0) return 0;
@@ -1003,7 +1084,7 @@ size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, i
   b += align256((size_t)bpad * 8);                 // nrm64
   b += align256((size_t)d * 8);                    // ctr
   b += align256(colmean_scratch_doubles(n, d) * 8);  // column-mean partials
-  b += align256((size_t)npad * ntb * 64 + 64);     // vf
+  b += kmm_vfrag_bytes(n, tmax);                   // vf, column scales
   b += align256(part_bytes_max(npad, mpad, ntb0, !square, ks, precision == GP_PREC_BF16X3));  // partials
   return b;
 }
@@ -1042,8 +1123,8 @@ bool kmm_plan_init(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n, 
   p.nrm64 = (double*)c; c += align256((size_t)bpad * 8);
   p.ctr = (double*)c;   c += align256((size_t)p.d * 8);
   p.cpart = (double*)c; c += align256(colmean_scratch_doubles(n, p.d) * 8);
-  const int ntb_alloc = (p.ntb + nt_launch(p.ntb) - 1) / nt_launch(p.ntb) * nt_launch(p.ntb);
-  p.vf = c;  c += align256((size_t)p.npad * ntb_alloc * 64 + 64);
+  carve_vfrag(p, c);
+  c += kmm_vfrag_bytes(n, tmax);
   p.part = (double*)c;
   return true;
 }
@@ -1092,7 +1173,8 @@ bool kmm_plan_model(KmmPlan& p, const gp_kernel* kern, int precision, int64_t n,
   char* c = (char*)model;
   p.xr = c;  c += align256((size_t)p.npad * p.ks * 64);
   p.nrm_b = (float*)c;  c += align256((size_t)p.npad * 4);
-  p.vf = c;  c += kmm_vfrag_bytes(n, tmax);
+  carve_vfrag(p, c);
+  c += kmm_vfrag_bytes(n, tmax);
   p.ctr = (double*)c;  c += align256((size_t)p.d * 8);
   p.cpart = (double*)c;  c += align256(colmean_scratch_doubles(n, p.d) * 8);
   if (m > 0) {
@@ -1400,11 +1482,6 @@ hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t 
   return hipGetLastError();
 }
 
-size_t kmm_vfrag_bytes(int64_t n, int t) {
-  const int ntb0 = (t + 15) / 16;
-  const int ntb = (ntb0 + nt_launch(ntb0) - 1) / nt_launch(ntb0) * nt_launch(ntb0);
-  return align256((size_t)round_up(n, 32) * ntb * 64 + 64);
-}
 
 template <int KS>
 static void launch_one(bool mixed, int nt, int kind, dim3 grid, const SweepArgs& a, hipStream_t st);
@@ -1464,9 +1541,12 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
   const int ntb_alloc = sc.groups * sc.nt;  // vf holds whole launch groups (zero padded)
   const int thr = 256;
   if (p.precision == GP_PREC_BF16X3) {
+    if (!p.vscale || !p.vinv || !p.vpart) return hipErrorInvalidValue;
+    vmax_partial_kernel<<<dim3(kVParts, (unsigned)t), 256, 0, st>>>(V, ldv, col0, p.n, p.vpart);
+    vscale_kernel<<<(unsigned)((t + 63) / 64), 64, 0, st>>>(p.vpart, t, p.vscale, p.vinv);
     const int64_t total = p.nchunks * ntb_alloc * 64;
-    prep_v_bf16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, col0, p.n, t, p.nchunks,
-                                                                               ntb_alloc, (bf16x8*)p.vf);
+    prep_v_f16x3_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, col0, p.vscale, p.n, t,
+                                                                              p.nchunks, ntb_alloc, (bf16x8*)p.vf);
   } else {
     const int64_t total = p.nchunks * ntb_alloc * 2 * 64;
     prep_v_fp32_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(V, ldv, col0, p.n, t, p.nchunks,
@@ -1535,9 +1615,10 @@ static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc,
   const dim3 egrid((unsigned)((p.m + 63) / 64), (unsigned)t);
   if (a.f32part)
     wide_epilogue_kernel<float><<<egrid, 256, 0, st>>>((const float*)p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf,
-                                                       out, ldo);
+                                                       p.vinv, out, ldo);
   else
-    wide_epilogue_kernel<double><<<egrid, 256, 0, st>>>(p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf, out, ldo);
+    wide_epilogue_kernel<double><<<egrid, 256, 0, st>>>(p.part, sc.nsplit, a.tpad, p.mpad, p.m, p.sf, p.vinv, out,
+                                                        ldo);
   return hipGetLastError();
 }
 
@@ -1591,7 +1672,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   const int thr = 256;
   const int64_t total = p.m * t;
   kmm_epilogue_kernel<<<(unsigned)((total + thr - 1) / thr), thr, 0, st>>>(
-      p.part, sc.nsplit, sc.tpad, p.mpad, p.m, t, p.sf, p.square ? p.sf + p.noise : 0.0,
+      p.part, sc.nsplit, sc.tpad, p.mpad, p.m, t, p.sf, p.square ? p.sf + p.noise : 0.0, mixed ? p.vinv : nullptr,
       p.square ? Vdiag : nullptr, ldv, out, ldo);
   return hipGetLastError();
 }

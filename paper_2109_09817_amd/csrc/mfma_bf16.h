@@ -1,5 +1,5 @@
-// Register types and helpers shared by the BF16X3 tile sweeps (K_hat V, the
-// hyperparameter forms and prediction).
+// Register types and helpers shared by the mixed-precision tile sweeps (K_hat V,
+// the hyperparameter forms and prediction).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,31 +42,50 @@ __device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& 
   }
 }
 
-// The same split with m - hi (exact in FP32) taken in one instruction
-// per value as the BF16 dot product of the packed hi pair with (-1, 0) or
-// (0, -1), added to m (an input below FP32's normal range may come out as m
-// itself; such a kernel value is far below any tolerance).  The (-1, 0) pair
-// is kept in a register: as an immediate the compiler encodes it as the inline
-// constant -1.0, whose bit pattern the hardware reads as (0, -1).
-__device__ __forceinline__ void split_bf16x8_dot2(const f32x8& m, bf16x8& H, bf16x8& L) {
-  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// Kernel values and vectors in the K_hat V products of the mixed form are FP16
+// hi + lo pairs of scaled values: the kernel value m in [0, 1] enters as
+// kMScale m (so that entries down to ~1e-9 stay in FP16's normal range) and each
+// column of V is scaled by a power of two that puts its largest entry in
+// [2^14, 2^15).  The partial sums are scaled back exactly in FP64.
+constexpr float kMScale = 32768.f;  // 2^15
+constexpr float kMaternC1s = (float)(32768.0 * M_LN2);              // 2^15 ln 2
+constexpr float kMaternC2s = (float)(32768.0 * M_LN2 * M_LN2 / 3.0);  // 2^15 (ln 2)^2 / 3
+
+// Split 8 FP32 values into FP16 hi = RNE(m) (two values per v_cvt_pk_f16_f32)
+// and lo = RNE(m - hi): v_fma_mixlo_f16 / v_fma_mixhi_f16 take hi's FP16 half as
+// an operand, form m - hi exactly in FP32 and round it into the low or high half
+// of the packed result, one instruction per value.  |m - hi| <= 2^-11 |m|, so
+// hi + lo holds m to 2^-22 relative (FP16 subnormals: absolute 2^-25 below 2^-14).
+// The two results are 16-byte units of the BF16 vector type (reinterpreted, as
+// for the point fragments).
+__device__ __forceinline__ uint32_t f16_residual_pair(uint32_t h, float m0, float m1) {
+  uint32_t l;
+  asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "=&v"(l)
+      : "v"(h), "v"(m0), "v"(m1));
+  return l;
+}
+
+__device__ __forceinline__ void split_f16x8(const f32x8& m, bf16x8& H, bf16x8& L) {
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
   typedef float f32x2 __attribute__((ext_vector_type(2)));
-  uint32_t neg_lo_bits = 0x0000bf80u;  // bf16 (-1, 0): low half -1, high half 0
-  asm("" : "+v"(neg_lo_bits));        // opaque to constant folding
-  const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, neg_lo_bits);
-  const bf16x2 neg_hi = __builtin_bit_cast(bf16x2, 0xbf800000u);  // bf16 (0, -1): the FP32 pattern of -1.0
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 h, l;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     const f32x2 v = {m[2 * p], m[2 * p + 1]};
-    const bf16x2 h = __builtin_convertvector(v, bf16x2);
-    const f32x2 r = {__builtin_amdgcn_fdot2_f32_bf16(h, neg_lo, v[0], false),
-                     __builtin_amdgcn_fdot2_f32_bf16(h, neg_hi, v[1], false)};
-    const bf16x2 l = __builtin_convertvector(r, bf16x2);
-    H[2 * p] = h[0];
-    H[2 * p + 1] = h[1];
-    L[2 * p] = l[0];
-    L[2 * p + 1] = l[1];
+    h[p] = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+    l[p] = f16_residual_pair(h[p], v[0], v[1]);
   }
+  H = __builtin_bit_cast(bf16x8, h);
+  L = __builtin_bit_cast(bf16x8, l);
+}
+
+// Value product on the FP16 matrix cores, operands held as 16-byte units.
+__device__ __forceinline__ f32x4 mfma_val(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                0, 0);
 }
 
 // Distance tile on the matrix cores: the point operands are FP16 (see the

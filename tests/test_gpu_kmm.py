@@ -13,8 +13,10 @@ pytestmark = pytest.mark.gpu
 
 # Relative error per vector ||got - ref|| / ||ref|| (the 1e-4 target; FP32 is held tighter).
 TOL = {"fp32": 2e-6, "bf16x3": 1e-4}
-# The same bound on the off-diagonal part s_f M V alone (K_hat V minus its exact diagonal).
-TOL_OFF = {"fp32": 2e-5, "bf16x3": 1e-4}
+# The bound on the off-diagonal part s_f M V alone (K_hat V minus its exact diagonal): the mixed
+# form's FP16 halves of distance, kernel values and V measure <= 2.2e-5 (the n = 917,504 model as
+# configured, where the distance's rounding dominates), so it is held to half the target.
+TOL_OFF = {"fp32": 2e-5, "bf16x3": 5e-5}
 
 
 def _run(kern_np, X, V, prec, Z=None):
