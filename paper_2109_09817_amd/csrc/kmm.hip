@@ -305,7 +305,9 @@ __global__ void prep_frag_fp32_kernel(const double* __restrict__ X, const double
 // scale[c] = 2^e with e = 15 - E, max |V_c| = f 2^E (f in [1/2, 1)), so that the
 // scaled column's largest entry lies in [2^14, 2^15), and inv[c] = 2^(-e - 15),
 // the factor that takes a partial sum of (kMScale m)(scale V) back to m V.  A zero
-// or non-finite column keeps scale 1.
+// or non-finite column keeps scale 1; e is clamped to [-1022, 1023], which only a
+// column whose largest entry lies below 2^-1008 reaches (its scaled entries then stay
+// below 2^15 and, down to 2^-1046 relative to that, in FP16's normal range).
 constexpr int kVParts = 64;
 
 __global__ __launch_bounds__(256) void vmax_partial_kernel(const double* __restrict__ V, int64_t ldv,
@@ -339,7 +341,7 @@ __global__ void vscale_kernel(const double* __restrict__ part, int t, double* __
     int E = 0;
     (void)frexp(mx, &E);
     e = 15 - E;
-    e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+    e = e < -1022 ? -1022 : (e > 1023 ? 1023 : e);  // 2^e and 2^(-e - 15) stay representable
   }
   scale[c] = ldexp(1.0, e);
   inv[c] = ldexp(1.0, -e - 15);

@@ -286,6 +286,38 @@ def test_products_do_not_depend_on_an_offset_of_the_data(prec):
     assert err_off <= TOL_OFF[prec] and errc <= TOL_OFF[prec]
 
 
+def test_mixed_form_columns_of_any_magnitude():
+    """The mixed form scales each column of V by a power of two before its FP16 split, so columns
+    of very different magnitudes (1e-300 to 1e300, a zero column, a column below FP32's range)
+    keep the accuracy of a unit column, and a non-finite entry stays in its own column.  (Arrays
+    here hold one column per row, as the other tests' do.)"""
+    n, d, t, m = 2500, 48, 9, 97
+    X, th, V = _case(n, d, t, True, seed=41)
+    V = V.copy()
+    mags = [1.0, 1e-300, 1e300, 0.0, 1e-45, 3.7e5, 1e-12, 1.0, 1.0]
+    for c, s in enumerate(mags):
+        V[c] *= s
+    Z = synth.query_molecule("c2", m, seed=8)[:, :d]
+    ref = ok.khat_matmul(X, th, V.T).T
+    refc = ok.cross_matmul(Z, X, th, V.T).T
+    got = _run(th, X, V, "bf16x3")
+    gotc = _run(th, X, V, "bf16x3", Z=Z)
+    diag = (th.sf + th.noise) * V
+    for c, s in enumerate(mags):
+        if s == 0.0:
+            assert not np.any(got[c]) and not np.any(gotc[c])
+            continue
+        # norms of the columns divided by their magnitude (squares of 1e-300 or 1e300 leave FP64)
+        g_off, r_off = (got - diag)[c] / s, (ref - diag)[c] / s
+        e_off = float(np.linalg.norm(g_off - r_off) / np.linalg.norm(r_off))
+        e_c = float(np.linalg.norm(gotc[c] / s - refc[c] / s) / np.linalg.norm(refc[c] / s))
+        print(f"column scale {s:.1e}: off-diagonal err {e_off:.3e}, cross err {e_c:.3e}", file=sys.stderr, flush=True)
+        assert e_off <= TOL_OFF["bf16x3"] and e_c <= TOL_OFF["bf16x3"]
+    V[8, 7] = np.nan
+    got = _run(th, X, V, "bf16x3")
+    assert np.all(np.isnan(got[8])) and np.all(np.isfinite(got[:8]))
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
 def test_products_with_an_outlying_first_point(prec):
     """The first training point moved 100 lengthscales away from the rest: the mixed form's centre is
