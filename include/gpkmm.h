@@ -64,7 +64,9 @@ extern "C" {
  * the scaled coordinates centred on the training points' column means m; the kernel
  * values enter as 2^15 m(r) and each column of V scaled by the power of two that puts
  * its largest entry in [2^14, 2^15), scalings undone exactly in FP64 (in gp_kmm_grad the
- * kernel-weighted values and the columns [x~ | x~^2] keep BF16 halves).  FP16 bounds the
+ * kernel-weighted values and the columns [x~ | x~^2] take FP16 halves after power-of-two
+ * scalings per wave's rows and per column, the operands of C = U diag(w) W^T BF16 halves).
+ * FP16 bounds the
  * scaled coordinates: |x_j - m_j| / l_j up to about 10^4
  * (Matern-5/2; about 3.8 10^4 for RBF), for training and query rows alike.  A point beyond
  * makes every product involving it NaN (gp_mbcg then fails with GP_ENONFINITE);

@@ -258,13 +258,15 @@ __global__ void grad_final_kernel(const double* __restrict__ part, int64_t npart
 
 __device__ __forceinline__ float bf16r(double x) { return (float)(__bf16)(float)x; }
 
-// BF16X3 fragments of the 2t columns [M1 | M2] (weighted by w when given), K
+// BF16X3 fragments of the 2t columns [M1 | M2] (weighted by w and, for point p,
+// scaled by pscale[p] when given), K
 // index 6t long.  A-operand role: [hi | hi | lo]; B-operand role: [hi | lo | hi],
 // so that sum_K A B = hi.hi + hi.lo + lo.hi over the 2t columns.  Fragment
 // (blk, q, lane) holds K = 32 q + 8 (lane/16) + j of point 16 blk + lane%16.
 __global__ void prep_pairfrag_bf16x3_kernel(const double* __restrict__ M1, const double* __restrict__ M2,
                                             int64_t ld, int64_t n, int t, const double* __restrict__ w,
-                                            int64_t nblk, int KSC, int b_role, bf16x8* __restrict__ out) {
+                                            const double* __restrict__ pscale, int64_t nblk, int KSC, int b_role,
+                                            bf16x8* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nblk * KSC * 64) return;
   const int lane = (int)(idx & 63);
@@ -273,6 +275,7 @@ __global__ void prep_pairfrag_bf16x3_kernel(const double* __restrict__ M1, const
   const int64_t blk = rest / KSC;
   const int64_t p = blk * 16 + (lane & 15);
   const int g = lane >> 4;
+  const double ps = pscale && p < n ? pscale[p] : 1.0;
   bf16x8 o;
   for (int j = 0; j < 8; ++j) {
     const int k = 32 * q + 8 * g + j;
@@ -281,7 +284,7 @@ __global__ void prep_pairfrag_bf16x3_kernel(const double* __restrict__ M1, const
       const int seg = k / (2 * t), cc = k - seg * 2 * t;
       const int c = cc < t ? cc : cc - t;
       const double* M = cc < t ? M1 : M2;
-      const double x = (w ? w[c] : 1.0) * M[(int64_t)c * ld + p];
+      const double x = ps * (w ? w[c] : 1.0) * M[(int64_t)c * ld + p];
       const float h = bf16r(x);
       const float l = bf16r(x - (double)h);
       v = b_role ? (seg == 1 ? l : h) : (seg == 2 ? l : h);
@@ -291,12 +294,17 @@ __global__ void prep_pairfrag_bf16x3_kernel(const double* __restrict__ M1, const
   out[idx] = o;
 }
 
-// BF16X3 fragments of the 2 NJ column blocks [x~ | x~^2] (each d columns padded
-// to 16 NJ) in the B-operand layout of the forms product: (chunk, cb, hl, lane)
-// -> 8 BF16 (hi or lo) of column 16 cb + lane%16 at the points 32 chunk + vperm(lane/16, j).
-__global__ void prep_formfrag_bf16x3_kernel(const double* __restrict__ X, int64_t n, int d, int nj,
-                                            const double* __restrict__ inv_ell, const double* __restrict__ mu,
-                                            int64_t nchunks, bf16x8* __restrict__ out) {
+// FP16 fragments of the 2 NJ column blocks [x~ | x~^2] (each d columns padded to
+// 16 NJ), every column scaled by its power of two (scal[j], scal[d + j]), in
+// the B-operand layout of the forms product: (chunk, cb, hl, lane) -> 8 FP16 (hi =
+// RNE16(v), lo = RNE16(v - hi)) of column 16 cb + lane%16 at the points
+// 32 chunk + vperm(lane/16, j).
+__device__ __forceinline__ double f16r(double x) { return (double)(_Float16)(float)x; }
+
+__global__ void prep_formfrag_f16x3_kernel(const double* __restrict__ X, int64_t n, int d, int nj,
+                                           const double* __restrict__ inv_ell, const double* __restrict__ mu,
+                                           const double* __restrict__ scal, int64_t nchunks,
+                                           bf16x8* __restrict__ out) {
   const int ng = 2 * nj;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nchunks * ng * 64) return;
@@ -307,20 +315,71 @@ __global__ void prep_formfrag_bf16x3_kernel(const double* __restrict__ X, int64_
   const bool square = cb >= nj;
   const int jj = 16 * (square ? cb - nj : cb) + (lane & 15);
   const int g = lane >> 4;
-  bf16x8 hi, lo;
+  const double sc = jj < d ? scal[(square ? d : 0) + jj] : 0.0;
+  f16x8 hi, lo;
   for (int j = 0; j < 8; ++j) {
     const int64_t b = ch * 32 + vperm(g, j);
     double v = 0.0;
     if (b < n && jj < d) {
       const double x = (X[b * d + jj] - mu[jj]) * inv_ell[jj];
-      v = square ? x * x : x;
+      v = (square ? x * x : x) * sc;
     }
-    const float h = bf16r(v);
-    hi[j] = (__bf16)h;
-    lo[j] = (__bf16)(float)(v - (double)h);
+    const double h = f16r(v);
+    hi[j] = (_Float16)(float)h;
+    lo[j] = (_Float16)(float)(v - h);
   }
-  out[(rest * 2 + 0) * 64 + lane] = hi;
-  out[(rest * 2 + 1) * 64 + lane] = lo;
+  out[(rest * 2 + 0) * 64 + lane] = __builtin_bit_cast(bf16x8, hi);
+  out[(rest * 2 + 1) * 64 + lane] = __builtin_bit_cast(bf16x8, lo);
+}
+
+// 2^e with e = 15 - E for x = f 2^E (f in [1/2, 1)): puts x in [2^14, 2^15); 1 for zero or non-finite x.
+__device__ __forceinline__ int pow2_exponent(double x) {
+  if (!(x > 0.0) || !(x <= 1.7976931348623157e308)) return 0;
+  int E = 0;
+  (void)frexp(x, &E);
+  const int e = 15 - E;
+  return e < -1022 ? -1022 : (e > 1023 ? 1023 : e);
+}
+
+// Column scalings of the forms product (layout in grad_tri.h), one block, thread j < d.
+// nmax[0] is the largest squared norm of the prescaled, centred coordinates
+// c (x - mean) / l of the distance operands, so that sqrt(nmax) / c bounds every
+// |x~_j| = |x_j - mean_j| / l_j: one bound for all columns (a column's values then lie
+// in FP16's normal range down to 2^-29 of it).
+__global__ void grad_scales_kernel(const double* __restrict__ nmax, double c, int d, double* __restrict__ scal) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  const double bx = sqrt(nmax[0]) / c;
+  const int ex = pow2_exponent(bx), esq = pow2_exponent(bx * bx);
+  scal[j] = ldexp(1.0, ex);
+  scal[d + j] = ldexp(1.0, esq);
+  scal[2 * d + j] = ldexp(1.0, -ex);
+  scal[3 * d + j] = ldexp(1.0, -esq);
+}
+
+// Group scalings of C^s: for each group of `grp` rows (one wave's rows: 16 or 32), s = 2^e
+// for the largest row bound sum_c |w_c| (|U_ac| max|W_c| + |W_ac| max|U_c|) of its rows
+// a < n (a group with none: 1); rs holds s for every row (the scale prep_pairfrag
+// applies), binv 1 / s per group.  One thread per row (mpad rows, a multiple of grp, in
+// blocks of 64 so that a group never straddles a wave); U, W column-major with leading
+// dimension n.
+__global__ __launch_bounds__(64) void grad_group_scale_kernel(const double* __restrict__ U,
+                                                              const double* __restrict__ W, int64_t n, int64_t mpad,
+                                                              int grp, int t, const double* __restrict__ w,
+                                                              const double* __restrict__ umax,
+                                                              const double* __restrict__ wmax,
+                                                              double* __restrict__ rs, double* __restrict__ binv) {
+  const int64_t a = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  double bound = 0.0;
+  if (a < n)
+    for (int c = 0; c < t; ++c)
+      bound += fabs(w[c]) * (fabs(U[(int64_t)c * n + a]) * wmax[c] + fabs(W[(int64_t)c * n + a]) * umax[c]);
+  for (int off = 1; off < grp; off <<= 1) bound = fmax(bound, __shfl_xor(bound, off, 64));
+  const int e = pow2_exponent(bound);
+  if (a < mpad) {
+    rs[a] = ldexp(1.0, e);
+    if (a % grp == 0) binv[a / grp] = ldexp(1.0, -e);
+  }
 }
 
 // First level of the unit reduction: block b sums units [b kRedUnits, ...) per entry.
@@ -430,6 +489,11 @@ size_t grad_ws_bytes(int precision, int d, int64_t n, int t) {
   b += align256(std::max((size_t)row_split(n, kDotBlocks).nblk * std::max(d, t), colmean_scratch_doubles(n, d)) *
                 8);  // reductions, column means
   b += align256((size_t)t * 8);                                  // U_c . W_c
+  if (g.mixed) {
+    b += align256(column_absmax_scratch_doubles(t) * 8) + 2 * align256((size_t)t * 8);  // max |U_c|, max |W_c|
+    b += align256(column_absmax_scratch_doubles(1) * 8) + align256(8) + align256((size_t)grad_scale_doubles(d) * 8);
+    b += 2 * align256((size_t)g.mpad * 8);                                                      // row-group scales
+  }
   return b + 4096;
 }
 
@@ -488,6 +552,18 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
                                            colmean_scratch_doubles(n, d)));
   double* uw = cv.take<double>(t);
   if (!uw) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace layout failed");
+  double *cmpart = nullptr, *umax = nullptr, *wmax = nullptr, *fpart = nullptr, *scal = nullptr;
+  double *rs = nullptr, *rinv = nullptr;
+  if (g.mixed) {
+    cmpart = cv.take<double>(column_absmax_scratch_doubles(t));
+    umax = cv.take<double>(t);
+    wmax = cv.take<double>(t);
+    fpart = cv.take<double>(column_absmax_scratch_doubles(1) + 32);  // norm-max scratch, then the max at the end
+    scal = cv.take<double>((size_t)grad_scale_doubles(d));
+    rs = cv.take<double>((size_t)g.mpad);
+    rinv = cv.take<double>((size_t)g.mpad);
+    if (!rinv) return fail(GP_EWORKSPACE, "gp_kmm_grad: workspace layout failed");
+  }
   std::vector<double> invh(d);
   for (int j = 0; j < d; ++j) invh[j] = 1.0 / kern->lengthscale[j];
   std::vector<int2> units;
@@ -509,14 +585,23 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
     GPK_HIP(hipMemcpyAsync(unit_dev, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice, st));
     const int64_t nbr = g.npad / 16, nba = g.mpad / 16;
     const int64_t tot = nbr * g.ksc * 64;
-    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot + thr - 1) / thr), thr, 0, st>>>(W, U, n, n, t, nullptr, nbr,
-                                                                                  g.ksc, 0, (bf16x8*)wf);
+    // scalings of the FP16 forms product: column maxima of U, W and of the form coordinates
+    GPK_HIP(column_absmax(U, n, n, t, cmpart, umax, st));
+    GPK_HIP(column_absmax(W, n, n, t, cmpart, wmax, st));
+    double* nmax = fpart + column_absmax_scratch_doubles(1);
+    GPK_HIP(column_absmax(dxn, g.mpad, g.mpad, 1, fpart, nmax, st));
+    grad_scales_kernel<<<1, 64, 0, st>>>(nmax, profile_coordinate_scale(kern->kind), d, scal);
+    const int grp = (int)(g.rows / kTriWaves);  // rows per wave
+    grad_group_scale_kernel<<<(unsigned)((g.mpad + 63) / 64), 64, 0, st>>>(U, W, n, g.mpad, grp, t, wdev, umax,
+                                                                           wmax, rs, rinv);
+    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot + thr - 1) / thr), thr, 0, st>>>(W, U, n, n, t, nullptr, nullptr,
+                                                                                  nbr, g.ksc, 0, (bf16x8*)wf);
     const int64_t tot2 = nba * g.ksc * 64;
-    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot2 + thr - 1) / thr), thr, 0, st>>>(U, W, n, n, t, wdev, nba,
+    prep_pairfrag_bf16x3_kernel<<<(unsigned)((tot2 + thr - 1) / thr), thr, 0, st>>>(U, W, n, n, t, wdev, rs, nba,
                                                                                    g.ksc, 1, (bf16x8*)uf);
     const int64_t tot3 = g.nchunks * g.ncb * 64;
-    prep_formfrag_bf16x3_kernel<<<(unsigned)((tot3 + thr - 1) / thr), thr, 0, st>>>(X, n, d, g.nj, inv_dev, mu,
-                                                                                   g.nchunks, (bf16x8*)gv);
+    prep_formfrag_f16x3_kernel<<<(unsigned)((tot3 + thr - 1) / thr), thr, 0, st>>>(X, n, d, g.nj, inv_dev, mu, scal,
+                                                                                  g.nchunks, (bf16x8*)gv);
     GPK_HIP(hipGetLastError());
     GradTriArgs a;
     a.xr = (const bf16x8*)dxr;
@@ -528,6 +613,8 @@ int run_kmm_grad(const gp_kernel* kern, int precision, const double* X, int64_t 
     a.X = X;
     a.mu = mu;
     a.inv_ell = inv_dev;
+    a.scal = scal;
+    a.grpinv = rinv;
     a.d = d;
     a.n = n;
     a.nchunks = g.nchunks;

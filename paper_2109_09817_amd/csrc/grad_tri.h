@@ -19,7 +19,8 @@
 //                                    hi.hi + hi.lo + lo.hi and the norm digits)
 //   C^s  = [W_b | U_b] . [w U_a | w W_a]^T   (K = 2t, split three ways)
 //   P    = psi(S) C^s, its row sums, and sum k(S) C^s   (registers, FP32)
-//   Q, T = P . [x~_b | x~_b^2]       (2 ceil(d/16) blocks of 16 columns)
+//   Q, T = P . [x~_b | x~_b^2]       (2 ceil(d/16) blocks of 16 columns; P and the
+//                                    columns as FP16 hi/lo of power-of-two scaled values)
 // Every 32 chunks the FP32 sums are folded into per-lane FP64 partials of
 //   g_j += sum_a x~_aj^2 R_a - 2 x~_aj Q_aj + T_aj,  R_a = sum_b P_ab.
 // The b-side fragments of each chunk are staged in LDS, double-buffered, and
@@ -36,8 +37,8 @@ struct GradTriArgs {
   const bf16x8* xr;     // b-stream FP16 distance fragments (A operand)
   const bf16x8* xc;     // a-row FP16 distance fragments (B operand)
   const bf16x8* cb;     // b-stream fragments of [W | U]        (A operand, K = 6t: hi | hi | lo)
-  const bf16x8* ca;     // a-row fragments of [w U | w W]       (B operand, K = 6t: hi | lo | hi)
-  const bf16x8* gv;     // b-stream fragments of [x~ | x~^2]    (B operand of the forms, hi and lo)
+  const bf16x8* ca;     // a-row fragments of [s_P w U | s_P w W]  (B operand, K = 6t: hi | lo | hi)
+  const bf16x8* gv;     // b-stream FP16 fragments of the scaled [x~ | x~^2]  (B operand of the forms, hi and lo)
   const int2* units;    // per workgroup: (row group, first chunk)
   const double* X;      // n x d row-major
   const double* mu;     // column means (d)
@@ -46,8 +47,20 @@ struct GradTriArgs {
   int64_t n;
   int64_t nchunks;
   int cps;              // chunk-range alignment of the units
+  const double* scal;   // column scalings of the FP16 forms (layout below)
+  const double* grpinv; // 1 / s for each wave's group of 16 NA rows (mpad / (16 NA) values)
   double* part;         // per unit: g_1..g_d, g_{s_f} (unscaled)
 };
+
+// Scalings of the mixed form's FP16 forms product P . [x~ | x~^2], P = psi (.) C^s.
+// The rows of C^s held by one wave (a group of 16 NA rows) enter scaled by the group's
+// s, the power of two that puts the largest of the rows' bounds
+// sum_c |w_c| (|U_ac| max|W_c| + |W_ac| max|U_c|) >= max_b |C^s_ab| in [2^14, 2^15) (one
+// scale per group: the wave's partial sums share it), and each form column by its own
+// power of two (largest entry in [2^14, 2^15)); the partial sums are scaled back
+// exactly.  Layout of the column array (4 d doubles):
+//   [j] scale of x~_j, [d + j] scale of x~_j^2, [2d + j] and [3d + j] their inverses.
+inline int grad_scale_doubles(int d) { return 4 * d; }
 
 // Waves per workgroup.  Two 4-wave workgroups share a CU: the per-chunk
 // barrier then keeps only half the CU's waves in step, and the other
@@ -60,7 +73,7 @@ constexpr int kTriFlush = 32;  // chunks per FP32 accumulation window
 // The largest C K-step count with two blocks per (KS, NJ) instantiation is read
 // off the compiled register counts.
 constexpr int tri_max_ksc2(int ks, int nj) {
-  return ks <= 4 && nj == 1 ? 12 : (ks <= 5 && nj <= 3 ? 8 : (ks == 7 && nj == 4 ? 2 : 0));
+  return ks <= 4 && nj == 1 ? 12 : (ks <= 4 && nj == 2 ? 8 : (ks == 5 && nj == 3 ? 8 : (ks == 7 && nj == 4 ? 2 : 0)));
 }
 constexpr int tri_na(int ks, int ksc, int nj) { return ksc <= tri_max_ksc2(ks, nj) ? 2 : 1; }
 // The C^s phase runs for both row blocks at once (each staged C fragment read

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
     for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  float sfacc = 0.f;
+  float sfacc = 0.f;  // sum of k (.) C^s over this wave's rows (in the wave's row scale)
   double g64[NJ];
 #pragma unroll
   for (int cb = 0; cb < NJ; ++cb) g64[cb] = 0.0;
@@ -84,6 +84,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
   };
   // Fold the FP32 window into the FP64 partials of g_j (j = 16 cb + c16).
   auto flush = [&]() {
+    const double bi = a.grpinv[ablk0 / NA];  // 1 / s of this wave's 16 NA rows
 #pragma unroll
     for (int ab = 0; ab < NA; ++ab) {
       const int64_t ar = (ablk0 + ab) * 16;
@@ -98,12 +99,13 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
         const int j = 16 * cb + c16;
         if (j < a.d) {
           const double m = a.mu[j], s = a.inv_ell[j];
+          const double qs = a.scal[2 * a.d + j], ts = a.scal[3 * a.d + j];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int64_t row = ar + 4 * g + i;
             if (row < a.n) {
               const double x = (a.X[row * a.d + j] - m) * s;
-              g64[cb] += x * x * Ri[i] - 2.0 * x * (double)acc[ab][cb][i] + (double)acc[ab][NJ + cb][i];
+              g64[cb] += (x * x * Ri[i] - 2.0 * x * ((double)acc[ab][cb][i] * qs) + (double)acc[ab][NJ + cb][i] * ts) * bi;
             }
           }
         }
@@ -112,8 +114,9 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
       for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    sf64 += (double)sfacc;
+    sf64 += (double)sfacc * bi;
     sfacc = 0.f;
+
   };
 
   fetch(c_begin, 0);
@@ -211,11 +214,12 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
           }
         }
         if (b0 < ar + 16) {  // straddles the block: keep b > a only
-          const int64_t am = ar + c16;
+          // point b0 + k against row ar + c16, in 32-bit offsets from b0 (ar - b0 lies in (-32, 16))
+          const int am = (int)(ar - b0) + c16;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            if (b0 + 4 * g + i <= am) q0[i] = 0.f;
-            if (b0 + 16 + 4 * g + i <= am) q1[i] = 0.f;
+            if (4 * g + i <= am) q0[i] = 0.f;
+            if (16 + 4 * g + i <= am) q1[i] = 0.f;
           }
         }
         f32x8 pv;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
           racc[ab] += p;
           sfacc = __builtin_fmaf(m, cs, sfacc);
         }
-        split_bf16x8(pv, H[ab], L[ab]);
+        split_f16x8(pv, H[ab], L[ab]);
       }
       bf16x8 Gh = stage[cur][TC::kDist + TC::kC + lane];
       bf16x8 Gl = stage[cur][TC::kDist + TC::kC + 64 + lane];
@@ -253,9 +257,9 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
         for (int ab = 0; ab < NA; ++ab) {
           if (!live[ab]) continue;
-          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gh, acc[ab][nb], 0, 0, 0);
-          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(H[ab], Gl, acc[ab][nb], 0, 0, 0);
-          acc[ab][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L[ab], Gh, acc[ab][nb], 0, 0, 0);
+          acc[ab][nb] = mfma_val(H[ab], Gh, acc[ab][nb]);
+          acc[ab][nb] = mfma_val(H[ab], Gl, acc[ab][nb]);
+          acc[ab][nb] = mfma_val(L[ab], Gh, acc[ab][nb]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (nb + 1 < NG) {

@@ -83,6 +83,9 @@ hipError_t kmm_prepare_v(const KmmPlan& p, const double* V, int64_t ldv, int t, 
 // diagonal term of the square product, ignored for cross products).
 hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, double* out, int64_t ldo,
                      hipStream_t st, bool row_independent);
+// The factor c of the prescaled coordinates x' = c (x - centre) / l, chosen so that the
+// profile reads r^2 through exp2: sqrt(5) log2(e) for Matern-5/2, sqrt(log2(e) / 2) for RBF.
+double profile_coordinate_scale(int kind);
 // The mixed form's FP16 distance operands of a square product (prep_frag_f16x3_kernel)
 // at ks K steps of 32 (ks * 32 >= 3d + 6), centred on ctr (d device values, the
 // column means of X): the b-side (xr) and a-side (xc) fragments of rows_pad points
@@ -94,6 +97,11 @@ hipError_t prep_dist(const gp_kernel* kern, const double* X, int64_t n, int64_t 
 // part: colmean_scratch_doubles(n, d) doubles of scratch.
 size_t colmean_scratch_doubles(int64_t n, int d);
 hipError_t column_means(const double* X, int64_t n, int d, double* part, double* mu, hipStream_t st);
+// Largest |V| of each of the t columns of V (column-major, ldv, n rows) into out (t
+// doubles, device); part: column_absmax_scratch_doubles(t) doubles of scratch.  NaN
+// entries are skipped.
+size_t column_absmax_scratch_doubles(int t);
+hipError_t column_absmax(const double* V, int64_t ldv, int64_t n, int t, double* part, double* out, hipStream_t st);
 // Bytes of the V fragments for t columns.
 size_t kmm_vfrag_bytes(int64_t n, int t);
 // A cross-product plan split in two: the training-side operands (b stream and V

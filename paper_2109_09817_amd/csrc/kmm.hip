@@ -347,6 +347,23 @@ __global__ void vscale_kernel(const double* __restrict__ part, int t, double* __
   inv[c] = ldexp(1.0, -e - 15);
 }
 
+__global__ void colmax_final_kernel(const double* __restrict__ part, int t, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t) return;
+  double mx = 0.0;
+  for (int q = 0; q < kVParts; ++q) mx = fmax(mx, part[(int64_t)c * kVParts + q]);
+  out[c] = mx;
+}
+
+size_t column_absmax_scratch_doubles(int t) { return (size_t)kVParts * (size_t)t; }
+
+hipError_t column_absmax(const double* V, int64_t ldv, int64_t n, int t, double* part, double* out, hipStream_t st) {
+  if (!V || !part || !out || t < 1 || n < 1) return hipErrorInvalidValue;
+  vmax_partial_kernel<<<dim3(kVParts, (unsigned)t), 256, 0, st>>>(V, ldv, nullptr, n, part);
+  colmax_final_kernel<<<(unsigned)((t + 63) / 64), 64, 0, st>>>(part, t, out);
+  return hipGetLastError();
+}
+
 // Mixed-form V fragments: (chunk, cb, hl, lane) -> 8 FP16 of v' = scale[c] V[b][c],
 // b = 32 chunk + vperm(g, j), c = 16 cb + lane%16; hl = 0: hi = RNE16(v'),
 // hl = 1: lo = RNE16(v' - hi).  Columns c >= t are zero.
@@ -1399,9 +1416,13 @@ static hipError_t sweep_fp64(const KmmPlan& p, const double* V, int64_t ldv, int
   return hipGetLastError();
 }
 
+double profile_coordinate_scale(int kind) {
+  return kind == GP_MATERN52 ? std::sqrt(5.0) * M_LOG2E : std::sqrt(0.5 * M_LOG2E);
+}
+
 static Scale make_scale(const gp_kernel* kern) {
   Scale s{};
-  const double c = kern->kind == GP_MATERN52 ? std::sqrt(5.0) * M_LOG2E : std::sqrt(0.5 * M_LOG2E);
+  const double c = profile_coordinate_scale(kern->kind);
   for (int j = 0; j < kern->d; ++j) s.s[j] = c / kern->lengthscale[j];
   return s;
 }
