@@ -53,7 +53,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
     for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  float sfacc = 0.f;  // sum of k (.) C^s over this wave's rows (in the wave's row scale)
+  float sfacc = 0.f;  // Matern: sum of S e C^s over this wave's rows (in the wave's row scale)
   double g64[NJ];
 #pragma unroll
   for (int cb = 0; cb < NJ; ++cb) g64[cb] = 0.0;
@@ -85,6 +85,13 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
   // Fold the FP32 window into the FP64 partials of g_j (j = 16 cb + c16).
   auto flush = [&]() {
     const double bi = a.grpinv[ablk0 / NA];  // 1 / s of this wave's 16 NA rows
+    // the s_f form: sum k C^s = sum p + kMaternC2 sum S e C^s (Matern), sum p (RBF)
+    double sfw = 0.0;
+#pragma unroll
+    for (int ab = 0; ab < NA; ++ab) sfw += (double)racc[ab];
+    if constexpr (KIND == GP_MATERN52) sfw += (double)kMaternC2 * (double)sfacc;
+    sf64 += sfw * bi;
+    sfacc = 0.f;
 #pragma unroll
     for (int ab = 0; ab < NA; ++ab) {
       const int64_t ar = (ablk0 + ab) * 16;
@@ -114,9 +121,6 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
 #pragma unroll
       for (int nb = 0; nb < NG; ++nb) acc[ab][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    sf64 += (double)sfacc * bi;
-    sfacc = 0.f;
-
   };
 
   fetch(c_begin, 0);
@@ -227,20 +231,20 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
         for (int k = 0; k < 8; ++k) {
           const float S = __builtin_fabsf(k < 4 ? s0[ab][k] : s1[ab][k - 4]);
           const float cs = k < 4 ? q0[k] : q1[k - 4];
-          float m, psi;
+          float p;  // psi C^s
           if constexpr (KIND == GP_MATERN52) {
+            // psi = (1 + sqrt5 r) e^{-sqrt5 r} and k = psi + (5 r^2 / 3) e^{-sqrt5 r}, so that
+            // k C^s = p + kMaternC2 S e C^s: the s_f sum keeps only S e C^s (added to the
+            // row sums of p at the flush)
             const float u = __builtin_amdgcn_sqrtf(S);
-            const float e = __builtin_amdgcn_exp2f(-u);
-            psi = __builtin_fmaf(u, kMaternC1, 1.0f) * e;  // (1 + sqrt5 r) e^{-sqrt5 r}
-            m = __builtin_fmaf(kMaternC2 * S, e, psi);     // (1 + sqrt5 r + 5r^2/3) e^{-sqrt5 r}
+            const float ec = __builtin_amdgcn_exp2f(-u) * cs;
+            p = __builtin_fmaf(u, kMaternC1, 1.0f) * ec;
+            sfacc = __builtin_fmaf(S, ec, sfacc);
           } else {
-            m = __builtin_amdgcn_exp2f(-S);
-            psi = m;
+            p = __builtin_amdgcn_exp2f(-S) * cs;  // psi = k: the s_f sum is the row sums of p
           }
-          const float p = psi * cs;
           pv[k] = p;
           racc[ab] += p;
-          sfacc = __builtin_fmaf(m, cs, sfacc);
         }
         split_f16x8(pv, H[ab], L[ab]);
       }
