@@ -15,7 +15,6 @@ struct TriChunk {
   static constexpr int kC = 2 * KSC * 64;
   static constexpr int kG = 2 * (2 * NJ) * 64;
   static constexpr int kAll = kDist + kC + kG;
-  static constexpr int kPerThread = (kAll + 64 * kTriWaves - 1) / (64 * kTriWaves);  // units per wave
 };
 
 template <int KS, int KSC, int NJ, int NA, int KIND>
@@ -59,28 +58,36 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
   for (int cb = 0; cb < NJ; ++cb) g64[cb] = 0.0;
   double sf64 = 0.0;
 
-  // Copy chunk ch into stage[buf] with direct global-to-LDS loads: each wave
-  // moves whole 64-lane units (16 bytes per lane, lane-contiguous in LDS), and
-  // the unit boundaries of the three streams are multiples of 64 lanes, so the
-  // source stream is uniform over the wave.  Completion is awaited (vmcnt) and
-  // published by the barrier that ends the iteration.
-  auto fetch = [&](int64_t ch, int buf) {
+  // Copy the chunks into stage[buf] with direct global-to-LDS loads: the 64-lane
+  // units (16 bytes per lane, lane-contiguous in LDS) of each of the three
+  // streams are dealt to the waves in turn (unit j of a stream to wave j mod 4),
+  // so the source stream and LDS slot of every load are fixed at compile time
+  // up to the wave index, which is held in a scalar register; the three stream
+  // pointers start at chunk c_begin and advance by one chunk per fetch.
+  // Completion is awaited (vmcnt) and published by the barrier that ends the
+  // iteration.
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  const int lofs = lane + 64 * wave;  // this lane's element of the wave's first unit
+  const bf16x8* px = a.xr + c_begin * (2 * KS * 64);
+  const bf16x8* pc = a.cb + c_begin * (2 * KSC * 64);
+  const bf16x8* pg = a.gv + c_begin * (2 * NG * 64);
+  auto load_stream = [&](const bf16x8* src, int units, int first, int buf) {
 #pragma unroll
-    for (int r = 0; r < TC::kPerThread; ++r) {
-      const int ub = 64 * (wave + kTriWaves * r);  // first unit slot of this wave
-      if (ub < TC::kAll) {
-        const bf16x8* src;
-        if (ub < TC::kDist) {
-          src = a.xr + (2 * ch * KS) * 64 + ub;
-        } else if (ub < TC::kDist + TC::kC) {
-          src = a.cb + (2 * ch * KSC) * 64 + (ub - TC::kDist);
-        } else {
-          src = a.gv + (ch * NG * 2) * 64 + (ub - TC::kDist - TC::kC);
-        }
-        __builtin_amdgcn_global_load_lds((const void*)(src + lane),
-                                         (__attribute__((address_space(3))) void*)&stage[buf][ub], 16, 0, 0);
-      }
+    for (int r = 0; r < (units + kTriWaves - 1) / kTriWaves; ++r) {
+      const int j = wu + kTriWaves * r;  // unit of the stream
+      if (j < units)
+        __builtin_amdgcn_global_load_lds((const void*)(src + lofs + 64 * kTriWaves * r),
+                                         (__attribute__((address_space(3))) void*)&stage[buf][first + 64 * j], 16, 0,
+                                         0);
     }
+  };
+  auto fetch = [&](int buf) {
+    load_stream(px, 2 * KS, 0, buf);
+    load_stream(pc, 2 * KSC, TC::kDist, buf);
+    load_stream(pg, 2 * NG, TC::kDist + TC::kC, buf);
+    px += 2 * KS * 64;
+    pc += 2 * KSC * 64;
+    pg += 2 * NG * 64;
   };
   // Fold the FP32 window into the FP64 partials of g_j (j = 16 cb + c16).
   auto flush = [&]() {
@@ -123,21 +130,27 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
     }
   };
 
-  fetch(c_begin, 0);
+  fetch(0);  // chunk c_begin
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int window = 0;
   for (int64_t ch = c_begin; ch < c_end; ++ch) {
     const int cur = (int)((ch - c_begin) & 1);
     const bool more = ch + 1 < c_end;
-    if (more) fetch(ch + 1, cur ^ 1);
+    if (more) fetch(cur ^ 1);  // chunk ch + 1
     const int64_t b0 = ch * 32;
     if (b0 + 31 > ablk0 * 16) {  // the first block's tile holds some pair b > a
+      // A later block with no pair b > a in this chunk (only where the chunk meets
+      // the wave's first rows) has all its pairs masked to zero below, so where
+      // the C^s phase runs for both blocks at once every block's tiles are
+      // computed and the MFMAs stay unconditional; the block-by-block form skips
+      // such a block (unconditional, it spills).
+      constexpr bool kJoint = tri_joint_c(KS, KSC, NJ);
       bool live[NA];
       f32x4 s0[NA], s1[NA];
 #pragma unroll
       for (int ab = 0; ab < NA; ++ab) {
-        live[ab] = b0 + 31 > (ablk0 + ab) * 16;
+        live[ab] = kJoint || b0 + 31 > (ablk0 + ab) * 16;
         s0[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
         s1[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
@@ -169,7 +182,6 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
       // C^s tiles: both blocks one staged K step at a time, the next step's
       // fragments read while these MFMAs run, where the registers allow;
       // otherwise block by block (the fragments re-read per block)
-      constexpr bool kJoint = tri_joint_c(KS, KSC, NJ);
       f32x4 q0a[NA], q1a[NA];
       if constexpr (kJoint) {
 #pragma unroll
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int ab = 0; ab < NA; ++ab) {
-            if (!live[ab]) continue;
+              if (!live[ab]) continue;
             q0a[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0f, CA[ab][q], q0a[ab], 0, 0, 0);
             q1a[ab] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1f, CA[ab][q], q1a[ab], 0, 0, 0);
           }
@@ -217,8 +229,9 @@ __global__ __launch_bounds__(64 * kTriWaves, 2) void grad_tri_bf16x3_kernel(Grad
                                                          q1, 0, 0, 0);
           }
         }
-        if (b0 < ar + 16) {  // straddles the block: keep b > a only
-          // point b0 + k against row ar + c16, in 32-bit offsets from b0 (ar - b0 lies in (-32, 16))
+        if (b0 < ar + 16) {  // meets or passes the block: keep b > a only
+          // point b0 + k against row ar + c16, in 32-bit offsets from b0 (ar - b0 lies in
+          // (-16, 16 NA + 15)); a block with b0 + 31 <= ar has every pair masked
           const int am = (int)(ar - b0) + c16;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
