@@ -278,7 +278,9 @@ int gp_lanczos_cache(const gp_kernel* kern, int32_t precision,
  * R.  X: device n x d; alpha: device n; R: device n x kc (ld n) or NULL;
  * Z: device m x d; mean: device m; var: device m (nullable; needs R).
  * Each row's result depends only on that row (not on the other rows of the
- * call).  Asynchronous.
+ * call).  Asynchronous.  GP_EINVAL for a NULL X, alpha, Z or mean, m < 1, or
+ * var without a cache, and GP_EWORKSPACE for a short workspace, all before
+ * any GPU work.
  */
 int gp_predict(const gp_kernel* kern, int32_t precision,
                const double* X, int64_t n, const double* alpha,

@@ -98,8 +98,12 @@ extern "C" int gp_predict(const gp_kernel* kern, int32_t precision, const double
                           size_t ws_bytes, void* stream) {
   GPK_TRY(check_predict_common(kern, precision, n, kc));
   if (!R) kc = 0;
+  // every argument is checked before the preparation's GPU work
+  if (!X || !alpha || !Z || !mean) return fail(GP_EINVAL, "gp_predict: NULL X, alpha, Z or mean");
+  if (m < 1) return fail(GP_EINVAL, "gp_predict: m must be >= 1");
+  if (var && kc < 1) return fail(GP_EINVAL, "gp_predict: variance needs a cache (R and kc >= 1)");
   const size_t mb = kmm_model_bytes(precision, kern->d, n, kc + 1);
-  const size_t rb = predict_run_bytes(precision, kern->d, n, m > 0 ? m : 1, kc);
+  const size_t rb = predict_run_bytes(precision, kern->d, n, m, kc);
   GPK_TRY(check_ws(ws, ws_bytes, align256(mb) + rb, "gp_predict"));
   GPK_TRY(gp_predict_prepare(kern, precision, X, n, alpha, R, kc, ws, mb, stream));
   return gp_predict_run(kern, precision, ws, n, kc, Z, m, mean, var, (char*)ws + align256(mb),

@@ -232,3 +232,112 @@ def test_exact_gp_entry_point_validates_on_the_host(lib):
     assert 2 * 8192 * 8192 * 8 <= b < 1.1 * 2 * 8192 * 8192 * 8
     assert lib.gp_workspace_bytes(_lib.GP_OP_EXACT, 65537, 0, 48, 0, 0, 1) == 0
     assert lib.gp_workspace_bytes(_lib.GP_OP_EXACT, 100, 0, 65, 0, 0, 1) == 0
+
+
+def test_bbmm_and_prediction_entry_points_validate_on_the_host(lib):
+    """Every argument error of the BBMM and prediction entry points is reported before any GPU work;
+    each call below either fails its argument checks or, with valid arguments, finds no workspace."""
+    from paper_2109_09817_amd import _lib
+    EINVAL, EWS = _lib.GP_EINVAL, _lib.GP_EWORKSPACE
+    k, keep = _kernel()
+    k0, keep0 = _kernel(noise=0.0)
+    k65, keep65 = _kernel(d=65)
+    fake = 4096  # never dereferenced: validation fails first
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+
+    # gp_kmm_grad: t in [1, 64], d <= 64, ld = n, finite column weights (read on the host)
+    g = np.zeros(6)
+    w = np.ones(64)
+
+    def grad(kern=k, prec=1, X=fake, n=10, ldu=10, ldw=10, t=2, colw=w):
+        return lib.gp_kmm_grad(C.byref(kern), prec, X, n, fake, ldu, fake, ldw, t, dp(colw), dp(g), None, 0, None)
+
+    assert grad(prec=7) == EINVAL and grad(X=None) == EINVAL and grad(n=0) == EINVAL
+    assert grad(t=0) == EINVAL and grad(t=65) == EINVAL and grad(kern=k65) == EINVAL
+    assert grad(ldu=9) == EINVAL and grad(ldw=11) == EINVAL
+    w_nan = np.ones(2)
+    w_nan[1] = np.nan
+    assert grad(colw=w_nan) == EINVAL and b"colw" in lib.gp_last_error()
+    assert grad() == EWS and grad(t=64) == EWS
+
+    # gp_pivchol_precond: k in [1, min(n, 1024)], noise > 0, outputs present
+    rank = C.c_int32(0)
+    ldp = C.c_double(0.0)
+
+    def piv(kern=k, n=10, kk=3, L=fake):
+        return lib.gp_pivchol_precond(C.byref(kern), fake, n, kk, L, fake, None, C.byref(rank), C.byref(ldp),
+                                      None, 0, None)
+
+    assert piv(kk=0) == EINVAL and piv(kk=11) == EINVAL and piv(n=2000, kk=1025) == EINVAL
+    assert piv(kern=k0) == EINVAL and piv(L=None) == EINVAL and piv(n=0) == EINVAL
+    assert piv() == EWS
+
+    # gp_probe_block has no workspace: only rejected calls are made
+    def probes(y=fake, n=10, t=3, L=fake, kk=2, noise=1e-2, B=fake):
+        return lib.gp_probe_block(y, n, t, L, kk, noise, 7, B, None)
+
+    assert probes(y=None) == EINVAL and probes(B=None) == EINVAL and probes(n=0) == EINVAL
+    assert probes(t=-1) == EINVAL and probes(t=256) == EINVAL
+    assert probes(kk=-1) == EINVAL and probes(kk=1025) == EINVAL and probes(L=None) == EINVAL
+    assert probes(noise=-1e-3) == EINVAL and probes(noise=float("nan")) == EINVAL
+
+    # gp_mbcg: s in [1, 256], max_iter >= 1, tol finite and >= 0, a consistent preconditioner
+    def mbcg(kern=k, prec=1, n=10, pc=None, B=fake, s=2, mi=5, tol=1e-6):
+        return lib.gp_mbcg(C.byref(kern), prec, fake, n, C.byref(pc) if pc is not None else None, B, s, mi, tol,
+                           fake, None, None, None, 0, None)
+
+    assert mbcg(prec=7) == EINVAL and mbcg(n=0) == EINVAL and mbcg(B=None) == EINVAL
+    assert mbcg(s=0) == EINVAL and mbcg(s=257) == EINVAL and mbcg(mi=0) == EINVAL
+    assert mbcg(tol=-1.0) == EINVAL and mbcg(tol=float("inf")) == EINVAL
+    assert mbcg(pc=_lib.GpPrecond(11, fake, fake)) == EINVAL  # rank > n
+    assert mbcg(pc=_lib.GpPrecond(3, None, fake)) == EINVAL
+    assert mbcg(kern=k0, pc=_lib.GpPrecond(3, fake, fake)) == EINVAL  # preconditioner without noise
+    assert mbcg() == EWS and mbcg(prec=_lib.GP_PREC_FP64) == EWS and mbcg(pc=_lib.GpPrecond(3, fake, fake)) == EWS
+
+    # gp_mll_and_grad: probes in [1, 255], rank in [0, min(n, 1024)], noise > 0
+    mll = C.c_double(0.0)
+
+    def mllg(kern=k, probes=4, rank=3, mi=20, prec=1, tol=1e-6, n=10, y=fake, opts=True):
+        o = _lib.GpMllOpts(probes, rank, mi, prec, tol, 1)
+        return lib.gp_mll_and_grad(C.byref(kern), C.byref(o) if opts else None, fake, y, n, C.byref(mll), dp(g),
+                                   None, None, 0, None)
+
+    assert mllg(opts=False) == EINVAL and mllg(prec=_lib.GP_PREC_FP64) == EINVAL
+    assert mllg(probes=0) == EINVAL and mllg(probes=256) == EINVAL
+    assert mllg(rank=-1) == EINVAL and mllg(rank=11) == EINVAL and mllg(mi=0) == EINVAL
+    assert mllg(tol=float("nan")) == EINVAL and mllg(kern=k0) == EINVAL and mllg(y=None) == EINVAL
+    assert mllg() == EWS and mllg(rank=0) == EWS
+
+    # gp_lanczos_cache: kc in [1, min(n, 4095)]
+    kco = C.c_int32(0)
+
+    def lanczos(n=10, kc=4, R=fake, prec=1):
+        return lib.gp_lanczos_cache(C.byref(k), prec, fake, fake, n, kc, R, C.byref(kco), None, 0, None)
+
+    assert lanczos(kc=0) == EINVAL and lanczos(kc=11) == EINVAL and lanczos(n=5000, kc=4096) == EINVAL
+    assert lanczos(R=None) == EINVAL and lanczos(prec=_lib.GP_PREC_FP64) == EINVAL
+    assert lanczos() == EWS
+
+    # prediction: model size, prepare, run and the one-call form
+    assert lib.gp_predict_model_bytes(C.byref(k), 1, 100, 16) > 0
+    assert lib.gp_predict_model_bytes(C.byref(k), 1, 100, -1) == 0
+    assert lib.gp_predict_model_bytes(C.byref(k), 1, 100, 4096) == 0
+    assert lib.gp_predict_model_bytes(C.byref(k65), 7, 100, 0) == 0
+    assert lib.gp_predict_prepare(C.byref(k), 1, fake, 10, fake, None, 4, fake, 1 << 30, None) == EINVAL  # kc, no R
+    assert lib.gp_predict_prepare(C.byref(k), 1, fake, 10, None, fake, 4, fake, 1 << 30, None) == EINVAL
+    assert lib.gp_predict_prepare(C.byref(k), 1, fake, 10, fake, fake, 4096, fake, 1 << 30, None) == EINVAL
+    assert lib.gp_predict_prepare(C.byref(k), 1, fake, 10, fake, fake, 4, None, 0, None) == EWS
+
+    def run(model=fake, kc=4, Z=fake, m=3, mean=fake, var=fake):
+        return lib.gp_predict_run(C.byref(k), 1, model, 10, kc, Z, m, mean, var, None, 0, None)
+
+    assert run(model=None) == EINVAL and run(Z=None) == EINVAL and run(mean=None) == EINVAL
+    assert run(m=0) == EINVAL and run(kc=0) == EINVAL  # a variance needs a cache
+    assert run() == EWS and run(kc=0, var=None) == EWS
+
+    def predict(R=fake, kc=4, Z=fake, m=3, mean=fake, var=fake):
+        return lib.gp_predict(C.byref(k), 1, fake, 10, fake, R, kc, Z, m, mean, var, None, 0, None)
+
+    assert predict(m=0) == EINVAL and predict(Z=None) == EINVAL and predict(mean=None) == EINVAL
+    assert predict(R=None) == EINVAL and b"variance" in lib.gp_last_error()  # var without a cache
+    assert predict() == EWS and predict(R=None, var=None) == EWS
