@@ -21,27 +21,6 @@ constexpr float kMaternC1 = (float)M_LN2;                  // ln 2
 constexpr float kMaternC2 = (float)(M_LN2 * M_LN2 / 3.0);  // (ln 2)^2 / 3
 // RBF: S = r^2 log2(e) / 2 so that exp(-r^2/2) = exp2(-S).
 
-// Split 8 FP32 values into BF16 hi = RNE(m) and lo = RNE(m - hi), two values per
-// v_cvt_pk_bf16_f32; hi is widened back with one shift or mask per value.
-__device__ __forceinline__ void split_bf16x8(const f32x8& m, bf16x8& H, bf16x8& L) {
-  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-  typedef float f32x2 __attribute__((ext_vector_type(2)));
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const f32x2 v = {m[2 * p], m[2 * p + 1]};
-    const bf16x2 h = __builtin_convertvector(v, bf16x2);
-    const uint32_t hb = __builtin_bit_cast(uint32_t, h);
-    const float h0 = __builtin_bit_cast(float, hb << 16);
-    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
-    const f32x2 r = {v[0] - h0, v[1] - h1};
-    const bf16x2 l = __builtin_convertvector(r, bf16x2);
-    H[2 * p] = h[0];
-    H[2 * p + 1] = h[1];
-    L[2 * p] = l[0];
-    L[2 * p + 1] = l[1];
-  }
-}
-
 // Kernel values and vectors in the K_hat V products of the mixed form are FP16
 // hi + lo pairs of scaled values: the kernel value m in [0, 1] enters as
 // kMScale m (so that entries down to ~1e-9 stay in FP16's normal range) and each
