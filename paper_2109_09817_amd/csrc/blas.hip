@@ -452,7 +452,7 @@ __global__ void argmax_partial_kernel(const double* __restrict__ delta, int64_t 
   si[threadIdx.x] = bi;
   __syncthreads();
   for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
+    if ((int)threadIdx.x < off) {
       const double ov = sv[threadIdx.x + off];
       const int64_t oi = si[threadIdx.x + off];
       const double mv = sv[threadIdx.x];
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void argmax_final_kernel(const double* __
   si[threadIdx.x] = bi;
   __syncthreads();
   for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
+    if ((int)threadIdx.x < off) {
       const double ov = sv[threadIdx.x + off];
       const int64_t oi = si[threadIdx.x + off];
       const double mv = sv[threadIdx.x];

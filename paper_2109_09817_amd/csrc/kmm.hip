@@ -1094,7 +1094,6 @@ size_t kmm_plan_bytes(int precision, int d, int64_t n, int64_t m, bool square, i
   const int64_t mpad = round_up(mrows, 256);
   const int64_t bpad = std::max(npad, mpad);  // the square case prepares mpad rows of X
   const int ntb0 = (tmax + 15) / 16;
-  const int ntb = (ntb0 + nt_launch(ntb0) - 1) / nt_launch(ntb0) * nt_launch(ntb0);
   size_t b = 0;
   b += align256((size_t)bpad * ks * 64);           // xr
   b += align256((size_t)mpad * ks * 64);           // xc
@@ -1587,8 +1586,8 @@ static void launch_wide(int kind, dim3 grid, const WideArgs& a, hipStream_t st) 
 }
 
 // Row-independent BF16X3 cross products (prediction): the wide sweep, same splits and partials.
-static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc, const double* Vdiag, int64_t ldv,
-                                 double* out, int64_t ldo, hipStream_t st) {
+static hipError_t kmm_sweep_wide(const KmmPlan& p, int t, const SplitChoice& sc, double* out, int64_t ldo,
+                                 hipStream_t st) {
   WideArgs a;
   a.xr = p.xr;
   a.xc = p.xc;
@@ -1653,7 +1652,7 @@ hipError_t kmm_sweep(const KmmPlan& p, int t, const double* Vdiag, int64_t ldv, 
   const int ntb = (t + 15) / 16;
   const SplitChoice sc = choose_split(p.npad, p.mpad, ntb, row_independent, p.ks, p.precision == GP_PREC_BF16X3);
   if (row_independent && mixed && !p.square && ntb <= 4 * kWideNB && p.ks <= 7)
-    return kmm_sweep_wide(p, t, sc, Vdiag, ldv, out, ldo, st);
+    return kmm_sweep_wide(p, t, sc, out, ldo, st);
   SweepArgs a;
   a.xr = p.xr;
   a.xc = p.xc;
